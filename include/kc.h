@@ -1,0 +1,145 @@
+/*
+ * kc.h -- exact and colour-sampled k-clique counting on one AMD Instinct MI355X.
+ *
+ * The method is the one of Finocchi, Finocchi & Fusco, "Clique counting in
+ * MapReduce: theory and experiments" (arXiv 1403.0734):
+ *   - nodes are totally ordered by (degree, label) (Section 2);
+ *   - every node u keeps its high-neighbourhood Gamma+(u), the neighbours above
+ *     it in that order (Section 2; Algorithm 1, round 1);
+ *   - every k-clique is counted once, by its smallest node u, as a (k-1)-clique
+ *     of the subgraph G+(u) induced by Gamma+(u) (Section 3, Algorithm 1 rounds
+ *     2-3, Theorem 1);
+ *   - colour sampling (cFFF_k, Section 6) keeps only monochromatic pairs of each
+ *     Gamma+(u) and scales the raw count back up.
+ *
+ * Conventions for every entry point:
+ *   - Plain C types only.  Every call returns kc_status: KC_OK (0) or a negative
+ *     error code; kc_status_str() gives a message (with the last HIP error text
+ *     for KC_EDEVICE).
+ *   - Node ids are uint32 in [0, n).  Per-node outputs are indexed by these
+ *     original ids.
+ *   - A kc_graph handle owns every device buffer it allocates; it is freed by
+ *     kc_graph_destroy().  A handle is used by one host thread at a time.
+ *   - All work runs on the HIP stream bound at creation (NULL = the default
+ *     stream).  Calls that return host scalars synchronise that stream before
+ *     returning; calls that write device arrays are ordered on the stream and
+ *     have completed when the call returns.
+ *   - Counts are exact uint64.  A total that does not fit in 64 bits is never
+ *     wrapped: the call returns KC_EOVERFLOW.
+ *   - Sizes: n < 2^32 and m_in < 2^31 (the canonicalisation sorts 2*m_in keys).
+ */
+#ifndef KC_H
+#define KC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t kc_status;
+typedef struct kc_graph kc_graph;
+
+enum {
+    KC_OK = 0,
+    KC_EINVAL = -1,    /* bad argument: null pointer, id >= n, k or c out of range */
+    KC_ESTATE = -2,    /* call out of order, e.g. counting before kc_orient */
+    KC_ENOMEM = -3,    /* device or host allocation failed */
+    KC_EOVERFLOW = -4, /* an exact count does not fit in uint64 */
+    KC_EDEVICE = -5    /* a HIP call failed */
+};
+
+/* Colour schemes for kc_count_colored. */
+enum {
+    KC_COLOR_PER_ROOT = 0, /* cFFF_k (Section 6): each root colours its own Gamma+(u);
+                              a k-clique survives with probability c^-(k-2) */
+    KC_COLOR_GLOBAL = 1    /* one colouring of all nodes; a k-clique survives when all
+                              k nodes share a colour, probability c^-(k-1) */
+};
+
+/* Scheduling policies (kc_set_schedule). */
+enum {
+    KC_SCHED_DEGREE = 0,  /* tier by out-degree, queue ordered by out-degree descending */
+    KC_SCHED_LEARNED = 1  /* tier and order from an MLP's predicted per-root work */
+};
+
+/* Largest clique size the counting kernels accept. */
+#define KC_KMAX 10
+
+typedef struct {
+    uint64_t raw;              /* cliques that survived the colouring (exact integer) */
+    double estimate;           /* raw * c^e rounded to nearest double, e = k-2 or k-1 */
+    uint64_t estimate_u64;     /* raw * c^e when it fits in 64 bits, else 0 */
+    int32_t estimate_fits_u64; /* 1 if estimate_u64 is exact */
+    int32_t scale_exponent;    /* e */
+} kc_estimate;
+
+/* Ingest (Section 2: the input is an edge set; degrees are computed here).
+ * src[i], dst[i] (i < m_in) are the endpoints of edge i.  Self-loops are dropped,
+ * each undirected pair is kept once, and d(u) is the degree in that simple graph.
+ * src/dst are device pointers if src_on_device != 0, else host pointers; they are
+ * read during the call only (the handle keeps its own copy).  hip_stream is a
+ * hipStream_t or NULL.  Errors: KC_EINVAL for null pointers, n == 0, an id >= n or
+ * m_in >= 2^31; KC_ENOMEM; KC_EDEVICE. */
+kc_status kc_graph_create(const uint32_t *src, const uint32_t *dst, uint64_t m_in, uint32_t n,
+                          int32_t src_on_device, void *hip_stream, kc_graph **out);
+
+/* Orientation (Section 2 total order; Algorithm 1, round 1): nodes are relabelled
+ * by their position in the (degree, label) order and every edge is kept once,
+ * from its smaller to its larger endpoint; each out-list is sorted.  Idempotent. */
+kc_status kc_orient(kc_graph *g);
+
+/* Exact q_k (Section 3, Theorem 1) for 1 <= k <= KC_KMAX: q_1 = n, q_2 = m, and for
+ * k >= 3 the sum over u of the (k-1)-cliques of G+(u).  KC_ESTATE if not oriented;
+ * KC_EOVERFLOW if q_k >= 2^64. */
+kc_status kc_count(const kc_graph *g, int32_t k, uint64_t *q_out);
+
+/* Colour-sampled estimate (Section 6, cFFF_k) for 3 <= k <= KC_KMAX and c >= 1.
+ * Colours depend on the original ids and on seed:
+ *   h = mix64(seed ^ mix64((u << 32) | x))  (per-root scheme, x in Gamma+(u)),
+ *   h = mix64(seed ^ mix64(x))              (global scheme),
+ *   colour = ((h >> 32) * c) >> 32,
+ * with mix64 the SplitMix64 finaliser.  c == 1 gives raw == q_k. */
+kc_status kc_count_colored(const kc_graph *g, int32_t k, uint32_t c, uint64_t seed, int32_t scheme,
+                           kc_estimate *out);
+
+/* Per-root counts q_{u,k-1} (Section 3: the count the reducer for u emits) into the
+ * caller's device array dev_counts[n], indexed by original id; optionally the
+ * per-root intersection work into dev_work[n] (may be NULL): the number of
+ * l-cliques of G+(u) for l = 1 .. k-2, i.e. the neighbourhood intersections an
+ * unpruned depth-first count performs.  3 <= k <= KC_KMAX. */
+kc_status kc_count_per_root(const kc_graph *g, int32_t k, uint64_t *dev_counts, uint64_t *dev_work);
+
+/* Exact q_k of num graphs in one batched, persistent launch sequence; q_out[i] is
+ * the count of gs[i].  Every graph must be oriented and bound to the same stream. */
+kc_status kc_count_batch(kc_graph *const *gs, uint32_t num, int32_t k, uint64_t *q_out);
+
+/* Scheduling policy for later counts.  For KC_SCHED_LEARNED, weights_path names a
+ * weight file written by kc_train_schedule (NULL keeps the weights already loaded). */
+kc_status kc_set_schedule(kc_graph *g, int32_t policy, const char *weights_path);
+
+/* Train the scheduler's MLP (8 features -> 32 -> 32 -> 1, ReLU, fp32) on GPU to
+ * predict log(1 + per-root work) at clique size k for the given graphs, for
+ * `epochs` full-batch Adam epochs, and write the weights to weights_path. */
+kc_status kc_train_schedule(kc_graph *const *gs, uint32_t num, int32_t k, int32_t epochs, uint64_t seed,
+                            const char *weights_path, float *final_loss);
+
+kc_status kc_graph_info(const kc_graph *g, uint32_t *n, uint64_t *m, uint32_t *max_outdeg);
+
+/* Copies of the handle's device arrays into caller device memory:
+ * the simple graph's CSR (row_ptr[n+1], col[2m]) and degrees deg[n]; the oriented
+ * CSR in rank space (optr[n+1], ocol[m]) and rank2id[n].  Any pointer may be NULL. */
+kc_status kc_get_csr(const kc_graph *g, uint64_t *row_ptr, uint32_t *col, uint32_t *deg);
+kc_status kc_get_oriented(const kc_graph *g, uint64_t *optr, uint32_t *ocol, uint32_t *rank2id);
+
+/* Stage timings of the last call (milliseconds, HIP events on the bound stream). */
+kc_status kc_last_timings(const kc_graph *g, float *ms_schedule, float *ms_count, float *ms_total);
+
+void kc_graph_destroy(kc_graph *g);
+const char *kc_status_str(kc_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KC_H */
