@@ -1,0 +1,258 @@
+// The C ABI of libkc: argument checks, handle life cycle, status codes.
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "kc_internal.h"
+
+namespace {
+thread_local char g_msg[512] = {0};
+std::mutex g_pool_mu;
+bool g_pool_ready[64] = {false};
+
+inline int bits_for(uint32_t n) {
+    int b = 1;
+    while (b < 32 && ((uint64_t)1 << b) < (uint64_t)n) ++b;
+    return b;
+}
+}  // namespace
+
+kc_status kc_fail(kc_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_msg, sizeof(g_msg), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+kc_status kc_hip_fail(hipError_t e, const char *what, const char *file, int line) {
+    const char *f = strrchr(file, '/');
+    snprintf(g_msg, sizeof(g_msg), "%s failed: %s (%s:%d)", what, hipGetErrorString(e), f ? f + 1 : file, line);
+    if (e == hipErrorOutOfMemory) return KC_ENOMEM;
+    return KC_EDEVICE;
+}
+
+kc_status kc_tmp_alloc(kc_tmp &t, size_t bytes, hipStream_t s) {
+    int dev = 0;
+    KC_HIP(hipGetDevice(&dev));
+    if (dev >= 0 && dev < 64 && !g_pool_ready[dev]) {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        if (!g_pool_ready[dev]) {
+            hipMemPool_t pool;
+            if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+                uint64_t thr = ~0ull;
+                (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+            }
+            g_pool_ready[dev] = true;
+        }
+    }
+    if (t.p) {
+        (void)hipFreeAsync(t.p, t.s);
+        t.p = nullptr;
+    }
+    t.s = s;
+    if (bytes == 0) bytes = 8;
+    KC_HIP(hipMallocAsync(&t.p, bytes, s));
+    return KC_OK;
+}
+
+extern "C" {
+
+const char *kc_status_str(kc_status s) {
+    static thread_local char buf[640];
+    const char *name = "unknown status";
+    switch (s) {
+        case KC_OK: name = "ok"; break;
+        case KC_EINVAL: name = "invalid argument"; break;
+        case KC_ESTATE: name = "call out of order"; break;
+        case KC_ENOMEM: name = "out of memory"; break;
+        case KC_EOVERFLOW: name = "count does not fit in 64 bits"; break;
+        case KC_EDEVICE: name = "device error"; break;
+    }
+    if (s != KC_OK && g_msg[0]) snprintf(buf, sizeof(buf), "%s: %s", name, g_msg);
+    else snprintf(buf, sizeof(buf), "%s", name);
+    return buf;
+}
+
+void kc_graph_destroy(kc_graph *g) {
+    if (!g) return;
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    else (void)hipDeviceSynchronize();
+    void *bufs[] = {g->rowptr, g->col, g->deg, g->ukeys, g->optr, g->ocol, g->rank2id, g->id2rank, g->mlp, g->d_res};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    if (g->h_res) (void)hipHostFree(g->h_res);
+    for (hipEvent_t e : g->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete g;
+}
+
+static kc_status create_impl(const uint32_t *src, const uint32_t *dst, uint64_t m_in, uint32_t n,
+                             int32_t src_on_device, void *hip_stream, kc_graph *g) {
+    KC_HIP(hipGetDevice(&g->device));
+    g->stream = (hipStream_t)hip_stream;
+    g->n = n;
+    g->m_in = m_in;
+    g->idbits = bits_for(n);
+    for (auto &e : g->ev) KC_HIP(hipEventCreate(&e));
+    KC_HIP(hipMalloc(&g->d_res, 64 * sizeof(uint64_t)));
+    KC_HIP(hipHostMalloc(&g->h_res, 64 * sizeof(uint64_t), hipHostMallocDefault));
+    const uint32_t *ds = src, *dd = dst;
+    kc_tmp cs, cd;
+    if (!src_on_device && m_in) {
+        KC_TRY(kc_tmp_alloc(cs, m_in * sizeof(uint32_t), g->stream));
+        KC_TRY(kc_tmp_alloc(cd, m_in * sizeof(uint32_t), g->stream));
+        KC_HIP(hipMemcpyAsync(cs.p, src, m_in * sizeof(uint32_t), hipMemcpyHostToDevice, g->stream));
+        KC_HIP(hipMemcpyAsync(cd.p, dst, m_in * sizeof(uint32_t), hipMemcpyHostToDevice, g->stream));
+        ds = cs.as<uint32_t>();
+        dd = cd.as<uint32_t>();
+    }
+    KC_TRY(kc_canonicalise(g, ds, dd));
+    KC_HIP(hipStreamSynchronize(g->stream));
+    return KC_OK;
+}
+
+kc_status kc_graph_create(const uint32_t *src, const uint32_t *dst, uint64_t m_in, uint32_t n,
+                          int32_t src_on_device, void *hip_stream, kc_graph **out) {
+    g_msg[0] = 0;
+    if (!out) return kc_fail(KC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n == 0) return kc_fail(KC_EINVAL, "n must be positive");
+    if (m_in && (!src || !dst)) return kc_fail(KC_EINVAL, "src or dst is NULL");
+    if (m_in >= (1ull << 31)) return kc_fail(KC_EINVAL, "m_in must be below 2^31");
+    kc_graph *g = new (std::nothrow) kc_graph();
+    if (!g) return kc_fail(KC_ENOMEM, "host allocation failed");
+    kc_status st = create_impl(src, dst, m_in, n, src_on_device, hip_stream, g);
+    if (st != KC_OK) {
+        kc_graph_destroy(g);
+        return st;
+    }
+    *out = g;
+    return KC_OK;
+}
+
+kc_status kc_orient(kc_graph *g) {
+    g_msg[0] = 0;
+    if (!g) return kc_fail(KC_EINVAL, "graph is NULL");
+    if (g->oriented) return KC_OK;
+    return kc_orient_impl(g);
+}
+
+static kc_status check_count(const kc_graph *g, int32_t k, int lo) {
+    if (!g) return kc_fail(KC_EINVAL, "graph is NULL");
+    if (k < lo || k > KC_KMAX) return kc_fail(KC_EINVAL, "k=%d outside [%d, %d]", k, lo, KC_KMAX);
+    if (!g->oriented) return kc_fail(KC_ESTATE, "kc_orient has not been called");
+    return KC_OK;
+}
+
+kc_status kc_count(const kc_graph *g, int32_t k, uint64_t *q_out) {
+    g_msg[0] = 0;
+    if (!q_out) return kc_fail(KC_EINVAL, "q_out is NULL");
+    KC_TRY(check_count(g, k, 1));
+    if (k == 1) {
+        *q_out = g->n;
+        return KC_OK;
+    }
+    if (k == 2) {
+        *q_out = g->m;
+        return KC_OK;
+    }
+    kc_count_args a;
+    a.k = k;
+    a.policy = g->policy;
+    uint64_t total = 0;
+    int ovf = 0;
+    KC_TRY(kc_count_impl(g, a, &total, &ovf));
+    if (ovf) return kc_fail(KC_EOVERFLOW, "q_%d >= 2^64", k);
+    *q_out = total;
+    return KC_OK;
+}
+
+kc_status kc_count_colored(const kc_graph *g, int32_t k, uint32_t c, uint64_t seed, int32_t scheme,
+                           kc_estimate *out) {
+    g_msg[0] = 0;
+    if (!out) return kc_fail(KC_EINVAL, "out is NULL");
+    KC_TRY(check_count(g, k, 3));
+    if (c == 0) return kc_fail(KC_EINVAL, "c must be at least 1");
+    if (scheme != KC_COLOR_PER_ROOT && scheme != KC_COLOR_GLOBAL) return kc_fail(KC_EINVAL, "unknown scheme %d", scheme);
+    kc_count_args a;
+    a.k = k;
+    a.colored = 1;
+    a.c = c;
+    a.seed = seed;
+    a.scheme = scheme;
+    a.policy = g->policy;
+    uint64_t raw = 0;
+    int ovf = 0;
+    KC_TRY(kc_count_impl(g, a, &raw, &ovf));
+    if (ovf) return kc_fail(KC_EOVERFLOW, "raw colour-sampled count >= 2^64");
+    const int e = scheme == KC_COLOR_PER_ROOT ? k - 2 : k - 1;
+    unsigned __int128 scale = 1, est = raw;
+    int fits128 = 1;
+    for (int i = 0; i < e; ++i) {
+        scale *= c;
+    }
+    // raw * c^e in 128 bits (raw < 2^64, c^e < 2^(32*8)): track overflow of 128 bits too
+    long double estd = (long double)raw;
+    for (int i = 0; i < e; ++i) estd *= (long double)c;
+    est = (unsigned __int128)raw;
+    for (int i = 0; i < e; ++i) {
+        if (est != 0 && (unsigned __int128)c > (~(unsigned __int128)0) / est) {
+            fits128 = 0;
+            break;
+        }
+        est *= c;
+    }
+    (void)scale;
+    out->raw = raw;
+    out->scale_exponent = e;
+    out->estimate = fits128 ? (double)est : (double)estd;
+    out->estimate_fits_u64 = (fits128 && (est >> 64) == 0) ? 1 : 0;
+    out->estimate_u64 = out->estimate_fits_u64 ? (uint64_t)est : 0;
+    return KC_OK;
+}
+
+kc_status kc_graph_info(const kc_graph *g, uint32_t *n, uint64_t *m, uint32_t *max_outdeg) {
+    g_msg[0] = 0;
+    if (!g) return kc_fail(KC_EINVAL, "graph is NULL");
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (max_outdeg) *max_outdeg = g->oriented ? g->max_outdeg : 0;
+    return KC_OK;
+}
+
+kc_status kc_get_csr(const kc_graph *g, uint64_t *row_ptr, uint32_t *col, uint32_t *deg) {
+    g_msg[0] = 0;
+    if (!g) return kc_fail(KC_EINVAL, "graph is NULL");
+    hipStream_t s = g->stream;
+    if (row_ptr) KC_HIP(hipMemcpyAsync(row_ptr, g->rowptr, ((size_t)g->n + 1) * 8, hipMemcpyDeviceToDevice, s));
+    if (col && g->m) KC_HIP(hipMemcpyAsync(col, g->col, 2 * (size_t)g->m * 4, hipMemcpyDeviceToDevice, s));
+    if (deg) KC_HIP(hipMemcpyAsync(deg, g->deg, (size_t)g->n * 4, hipMemcpyDeviceToDevice, s));
+    KC_HIP(hipStreamSynchronize(s));
+    return KC_OK;
+}
+
+kc_status kc_get_oriented(const kc_graph *g, uint64_t *optr, uint32_t *ocol, uint32_t *rank2id) {
+    g_msg[0] = 0;
+    if (!g) return kc_fail(KC_EINVAL, "graph is NULL");
+    if (!g->oriented) return kc_fail(KC_ESTATE, "kc_orient has not been called");
+    hipStream_t s = g->stream;
+    if (optr) KC_HIP(hipMemcpyAsync(optr, g->optr, ((size_t)g->n + 1) * 8, hipMemcpyDeviceToDevice, s));
+    if (ocol && g->m) KC_HIP(hipMemcpyAsync(ocol, g->ocol, (size_t)g->m * 4, hipMemcpyDeviceToDevice, s));
+    if (rank2id) KC_HIP(hipMemcpyAsync(rank2id, g->rank2id, (size_t)g->n * 4, hipMemcpyDeviceToDevice, s));
+    KC_HIP(hipStreamSynchronize(s));
+    return KC_OK;
+}
+
+kc_status kc_last_timings(const kc_graph *g, float *ms_schedule, float *ms_count, float *ms_total) {
+    if (!g) return kc_fail(KC_EINVAL, "graph is NULL");
+    if (ms_schedule) *ms_schedule = g->t_schedule;
+    if (ms_count) *ms_count = g->t_count;
+    if (ms_total) *ms_total = g->t_total;
+    return KC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,246 @@
+// Ingest (simple graph + degrees) and the degree-ordered orientation.
+//
+// Ingest (Section 2: the input is an edge set whose endpoints carry degrees):
+//   every input edge (u, v), u != v, becomes the two keys (u, v) and (v, u);
+//   a radix sort and a neighbour-difference flag leave each directed pair once,
+//   which is the symmetric CSR of the simple graph; d(u) is the row length.
+// Orientation (Section 2 total order; Algorithm 1 round 1):
+//   nodes are sorted by (d(u), u) and relabelled by position (rank); every CSR
+//   entry u -> v with (d(u), u) < (d(v), v) becomes the rank pair
+//   (rank(u), rank(v)); a second radix sort of those pairs is the oriented CSR,
+//   out-lists ascending in rank, i.e. in the paper's order.
+#include "kc_internal.h"
+
+namespace {
+
+constexpr int T = 256;
+
+inline unsigned grid_for(size_t n, int per = T) { return (unsigned)((n + per - 1) / per); }
+
+__global__ void k_make_keys(const uint32_t *src, const uint32_t *dst, size_t m_in, uint32_t n, int B,
+                            uint64_t sentinel, uint64_t *keys, uint32_t *err) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m_in) return;
+    const uint32_t u = src[i], v = dst[i];
+    uint64_t k0 = sentinel, k1 = sentinel;
+    if (u >= n || v >= n) {
+        atomicOr(err, 1u);
+    } else if (u != v) {
+        k0 = ((uint64_t)u << B) | v;
+        k1 = ((uint64_t)v << B) | u;
+    }
+    keys[2 * i] = k0;
+    keys[2 * i + 1] = k1;
+}
+
+// flag[i] = 1 for the first copy of each key that is not the sentinel
+__global__ void k_unique_flags(const uint64_t *keys, size_t N, uint64_t sentinel, uint32_t *flag) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const uint64_t k = keys[i];
+    flag[i] = (k != sentinel && (i == 0 || keys[i - 1] != k)) ? 1u : 0u;
+}
+
+__global__ void k_compact_u64(const uint64_t *in, const uint32_t *flag, const uint32_t *pos, size_t N,
+                              uint64_t *out) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    if (flag[i]) out[pos[i]] = in[i];
+}
+
+// Row pointers of a CSR given its keys sorted by row (row = key >> B):
+// rowptr[r] = first position whose row is >= r, rowptr[n] = M.
+__global__ void k_rowptr(const uint64_t *keys, size_t M, int B, uint32_t n, uint64_t *rowptr) {
+    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= M) return;
+    const int64_t r = (int64_t)(keys[p] >> B);
+    const int64_t rp = p == 0 ? -1 : (int64_t)(keys[p - 1] >> B);
+    for (int64_t x = rp + 1; x <= r; ++x) rowptr[x] = p;
+    if (p == M - 1)
+        for (int64_t x = r + 1; x <= (int64_t)n; ++x) rowptr[x] = M;
+}
+
+__global__ void k_fill_u64(uint64_t *p, size_t n, uint64_t v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_low_bits(const uint64_t *keys, size_t M, uint64_t mask, uint32_t *out) {
+    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < M) out[p] = (uint32_t)(keys[p] & mask);
+}
+
+__global__ void k_row_lengths(const uint64_t *rowptr, uint32_t n, uint32_t *len, uint32_t *maxlen) {
+    const size_t x = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t l = 0;
+    if (x < n) {
+        l = (uint32_t)(rowptr[x + 1] - rowptr[x]);
+        if (len) len[x] = l;
+    }
+    if (maxlen) {
+        l = kc_wave_max_u32(l);
+        if ((threadIdx.x & 63) == 0) atomicMax(maxlen, l);
+    }
+}
+
+// node key (d(x), x): the paper's order as one integer
+__global__ void k_node_keys(const uint32_t *deg, uint32_t n, int B, uint64_t *keys) {
+    const size_t x = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) keys[x] = ((uint64_t)deg[x] << B) | x;
+}
+
+__global__ void k_ranks(const uint64_t *sorted, uint32_t n, uint64_t mask, uint32_t *rank2id, uint32_t *id2rank) {
+    const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const uint32_t id = (uint32_t)(sorted[r] & mask);
+    rank2id[r] = id;
+    id2rank[id] = (uint32_t)r;
+}
+
+// keep u -> v iff (d(u), u) < (d(v), v)
+__global__ void k_orient_flags(const uint64_t *ukeys, size_t M, int B, uint64_t mask, const uint32_t *deg,
+                               uint32_t *flag) {
+    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= M) return;
+    const uint32_t u = (uint32_t)(ukeys[p] >> B), v = (uint32_t)(ukeys[p] & mask);
+    const uint32_t du = deg[u], dv = deg[v];
+    flag[p] = (du < dv || (du == dv && u < v)) ? 1u : 0u;
+}
+
+__global__ void k_orient_emit(const uint64_t *ukeys, const uint32_t *flag, const uint32_t *pos, size_t M, int B,
+                              uint64_t mask, const uint32_t *id2rank, uint64_t *okeys) {
+    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= M || !flag[p]) return;
+    const uint32_t u = (uint32_t)(ukeys[p] >> B), v = (uint32_t)(ukeys[p] & mask);
+    okeys[pos[p]] = ((uint64_t)id2rank[u] << B) | id2rank[v];
+}
+
+kc_status rows_from_sorted(const uint64_t *keys, size_t M, int B, uint32_t n, uint64_t *rowptr, hipStream_t s) {
+    if (M == 0) {
+        hipLaunchKernelGGL(k_fill_u64, dim3(grid_for((size_t)n + 1)), dim3(T), 0, s, rowptr, (size_t)n + 1, 0ull);
+    } else {
+        hipLaunchKernelGGL(k_rowptr, dim3(grid_for(M)), dim3(T), 0, s, keys, M, B, n, rowptr);
+    }
+    KC_HIP(hipGetLastError());
+    return KC_OK;
+}
+
+}  // namespace
+
+kc_status kc_canonicalise(kc_graph *g, const uint32_t *d_src, const uint32_t *d_dst) {
+    hipStream_t s = g->stream;
+    const uint32_t n = g->n;
+    const int B = g->idbits;
+    const size_t N = 2 * (size_t)g->m_in;
+    const uint64_t mask = (B >= 64) ? ~0ull : ((1ull << B) - 1ull);
+    const uint64_t sentinel = (2 * B >= 64) ? ~0ull : ((1ull << (2 * B)) - 1ull);
+
+    KC_HIP(hipMalloc(&g->rowptr, ((size_t)n + 1) * sizeof(uint64_t)));
+    KC_HIP(hipMalloc(&g->deg, (size_t)n * sizeof(uint32_t)));
+
+    kc_tmp keys, tmp, flag, pos, err, total;
+    KC_TRY(kc_tmp_alloc(err, sizeof(uint32_t) * 2, s));
+    KC_TRY(kc_tmp_alloc(total, sizeof(uint32_t) * 2, s));
+    KC_HIP(hipMemsetAsync(err.p, 0, sizeof(uint32_t) * 2, s));
+    uint32_t M2 = 0;
+    if (N > 0) {
+        KC_TRY(kc_tmp_alloc(keys, N * sizeof(uint64_t), s));
+        KC_TRY(kc_tmp_alloc(tmp, N * sizeof(uint64_t), s));
+        hipLaunchKernelGGL(k_make_keys, dim3(grid_for(g->m_in)), dim3(T), 0, s, d_src, d_dst, (size_t)g->m_in, n, B,
+                           sentinel, keys.as<uint64_t>(), err.as<uint32_t>());
+        KC_HIP(hipGetLastError());
+        uint32_t h_err = 0;
+        KC_HIP(hipMemcpyAsync(&h_err, err.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        KC_HIP(hipStreamSynchronize(s));
+        if (h_err) return kc_fail(KC_EINVAL, "an edge endpoint is >= n (%u)", n);
+        KC_TRY(kc_radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), N, 0, 2 * B, s));
+        KC_TRY(kc_tmp_alloc(flag, N * sizeof(uint32_t), s));
+        KC_TRY(kc_tmp_alloc(pos, N * sizeof(uint32_t), s));
+        hipLaunchKernelGGL(k_unique_flags, dim3(grid_for(N)), dim3(T), 0, s, keys.as<uint64_t>(), N, sentinel,
+                           flag.as<uint32_t>());
+        KC_HIP(hipGetLastError());
+        KC_TRY(kc_scan_excl_u32(flag.as<uint32_t>(), pos.as<uint32_t>(), N, total.as<uint32_t>(), s));
+        KC_HIP(hipMemcpyAsync(&M2, total.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        KC_HIP(hipStreamSynchronize(s));
+        // the unique keys stay on the handle until the orientation has used them
+        KC_HIP(hipMalloc(&g->ukeys, (size_t)(M2 ? M2 : 1) * sizeof(uint64_t)));
+        hipLaunchKernelGGL(k_compact_u64, dim3(grid_for(N)), dim3(T), 0, s, keys.as<uint64_t>(), flag.as<uint32_t>(),
+                           pos.as<uint32_t>(), N, g->ukeys);
+        KC_HIP(hipGetLastError());
+    }
+    g->m = M2 / 2;
+    KC_HIP(hipMalloc(&g->col, (size_t)(M2 ? M2 : 1) * sizeof(uint32_t)));
+    const uint64_t *uk = g->ukeys;
+    KC_TRY(rows_from_sorted(uk, M2, B, n, g->rowptr, s));
+    if (M2) {
+        hipLaunchKernelGGL(k_low_bits, dim3(grid_for(M2)), dim3(T), 0, s, uk, (size_t)M2, mask, g->col);
+        KC_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_row_lengths, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)g->rowptr, n, g->deg,
+                       (uint32_t *)nullptr);
+    KC_HIP(hipGetLastError());
+    KC_HIP(hipStreamSynchronize(s));
+    return KC_OK;
+}
+
+kc_status kc_orient_impl(kc_graph *g) {
+    hipStream_t s = g->stream;
+    const uint32_t n = g->n;
+    const int B = g->idbits;
+    const uint64_t mask = (B >= 64) ? ~0ull : ((1ull << B) - 1ull);
+    const size_t M2 = 2 * (size_t)g->m;
+
+    KC_HIP(hipMalloc(&g->optr, ((size_t)n + 1) * sizeof(uint64_t)));
+    KC_HIP(hipMalloc(&g->ocol, (size_t)(g->m ? g->m : 1) * sizeof(uint32_t)));
+    KC_HIP(hipMalloc(&g->rank2id, (size_t)n * sizeof(uint32_t)));
+    KC_HIP(hipMalloc(&g->id2rank, (size_t)n * sizeof(uint32_t)));
+
+    // 1. ranks: stable sort of (d(x) << B | x) on the degree bits (ids already ascending)
+    kc_tmp nk, nk_tmp;
+    KC_TRY(kc_tmp_alloc(nk, (size_t)n * sizeof(uint64_t), s));
+    KC_TRY(kc_tmp_alloc(nk_tmp, (size_t)n * sizeof(uint64_t), s));
+    hipLaunchKernelGGL(k_node_keys, dim3(grid_for(n)), dim3(T), 0, s, (const uint32_t *)g->deg, n, B,
+                       nk.as<uint64_t>());
+    KC_HIP(hipGetLastError());
+    KC_TRY(kc_radix_sort_u64(nk.as<uint64_t>(), nk_tmp.as<uint64_t>(), n, B, 2 * B, s));
+    hipLaunchKernelGGL(k_ranks, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)nk.as<uint64_t>(), n, mask,
+                       g->rank2id, g->id2rank);
+    KC_HIP(hipGetLastError());
+
+    // 2. keep each edge once, from lower to higher key, in rank space
+    kc_tmp flag, pos, okeys, otmp, maxd;
+    KC_TRY(kc_tmp_alloc(maxd, sizeof(uint32_t), s));
+    KC_HIP(hipMemsetAsync(maxd.p, 0, sizeof(uint32_t), s));
+    const size_t m = g->m;
+    if (m > 0) {
+        KC_TRY(kc_tmp_alloc(flag, M2 * sizeof(uint32_t), s));
+        KC_TRY(kc_tmp_alloc(pos, M2 * sizeof(uint32_t), s));
+        KC_TRY(kc_tmp_alloc(okeys, m * sizeof(uint64_t), s));
+        KC_TRY(kc_tmp_alloc(otmp, m * sizeof(uint64_t), s));
+        hipLaunchKernelGGL(k_orient_flags, dim3(grid_for(M2)), dim3(T), 0, s, (const uint64_t *)g->ukeys,
+                           M2, B, mask, (const uint32_t *)g->deg, flag.as<uint32_t>());
+        KC_HIP(hipGetLastError());
+        KC_TRY(kc_scan_excl_u32(flag.as<uint32_t>(), pos.as<uint32_t>(), M2, nullptr, s));
+        hipLaunchKernelGGL(k_orient_emit, dim3(grid_for(M2)), dim3(T), 0, s, (const uint64_t *)g->ukeys,
+                           (const uint32_t *)flag.as<uint32_t>(), (const uint32_t *)pos.as<uint32_t>(), M2, B, mask,
+                           (const uint32_t *)g->id2rank, okeys.as<uint64_t>());
+        KC_HIP(hipGetLastError());
+        KC_TRY(kc_radix_sort_u64(okeys.as<uint64_t>(), otmp.as<uint64_t>(), m, 0, 2 * B, s));
+        hipLaunchKernelGGL(k_low_bits, dim3(grid_for(m)), dim3(T), 0, s, (const uint64_t *)okeys.as<uint64_t>(), m,
+                           mask, g->ocol);
+        KC_HIP(hipGetLastError());
+    }
+    KC_TRY(rows_from_sorted(okeys.as<uint64_t>(), m, B, n, g->optr, s));
+    hipLaunchKernelGGL(k_row_lengths, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)g->optr, n,
+                       (uint32_t *)nullptr, maxd.as<uint32_t>());
+    KC_HIP(hipGetLastError());
+    KC_HIP(hipMemcpyAsync(&g->max_outdeg, maxd.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    KC_HIP(hipStreamSynchronize(s));
+    if (g->ukeys) {
+        KC_HIP(hipFree(g->ukeys));
+        g->ukeys = nullptr;
+    }
+    g->oriented = 1;
+    return KC_OK;
+}
+

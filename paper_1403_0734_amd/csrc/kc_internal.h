@@ -1,0 +1,172 @@
+// Internal declarations of libkc (gfx950, wave64).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "kc.h"
+
+// ----------------------------------------------------------------------------
+// Error plumbing
+kc_status kc_fail(kc_status s, const char *fmt, ...);
+kc_status kc_hip_fail(hipError_t e, const char *what, const char *file, int line);
+
+#define KC_HIP(x)                                                      \
+    do {                                                               \
+        hipError_t kc_e_ = (x);                                        \
+        if (kc_e_ != hipSuccess) return kc_hip_fail(kc_e_, #x, __FILE__, __LINE__); \
+    } while (0)
+
+#define KC_TRY(x)                        \
+    do {                                 \
+        kc_status kc_s_ = (x);           \
+        if (kc_s_ != KC_OK) return kc_s_; \
+    } while (0)
+
+// ----------------------------------------------------------------------------
+// Stream-ordered temporary allocation (the device's default memory pool, with
+// its release threshold raised so that memory is reused across calls).
+struct kc_tmp {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    kc_tmp() = default;
+    kc_tmp(const kc_tmp &) = delete;
+    kc_tmp &operator=(const kc_tmp &) = delete;
+    ~kc_tmp() {
+        if (p) (void)hipFreeAsync(p, s);
+    }
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+kc_status kc_tmp_alloc(kc_tmp &t, size_t bytes, hipStream_t s);
+
+// ----------------------------------------------------------------------------
+// The handle.
+struct kc_graph {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint32_t n = 0;
+    uint64_t m_in = 0;
+    uint64_t m = 0;       // undirected edges of the simple graph
+    int idbits = 1;       // bits that hold any id in [0, n)
+
+    // simple graph (symmetric CSR) and degrees
+    uint64_t *rowptr = nullptr;  // n + 1
+    uint32_t *col = nullptr;     // 2m
+    uint32_t *deg = nullptr;     // n
+    uint64_t *ukeys = nullptr;   // 2m sorted (row << idbits | col) keys, held from ingest to orientation
+
+    // orientation, rank space
+    int oriented = 0;
+    uint64_t *optr = nullptr;     // n + 1
+    uint32_t *ocol = nullptr;     // m
+    uint32_t *rank2id = nullptr;  // n
+    uint32_t *id2rank = nullptr;  // n
+    uint32_t max_outdeg = 0;
+
+    // schedule
+    int policy = KC_SCHED_DEGREE;
+    float *mlp = nullptr;  // device weights (KC_MLP_PARAMS floats)
+    int mlp_loaded = 0;
+
+    // small result area: device + pinned host mirror
+    uint64_t *d_res = nullptr;  // [0] total, [1] overflow flag, [2..] misc
+    uint64_t *h_res = nullptr;
+
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    float t_schedule = 0.f, t_count = 0.f, t_total = 0.f;
+};
+
+// ----------------------------------------------------------------------------
+// Device-wide primitives (kc_prims.hip)
+kc_status kc_scan_excl_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *d_total, hipStream_t s);
+kc_status kc_scan_excl_u64(const uint64_t *in, uint64_t *out, size_t n, uint64_t *d_total, hipStream_t s);
+// Stable LSD radix sort of 64-bit keys on bits [bit_lo, bit_hi).  Sorted keys end
+// in *keys (tmp is a same-sized buffer).
+kc_status kc_radix_sort_u64(uint64_t *keys, uint64_t *tmp, size_t n, int bit_lo, int bit_hi, hipStream_t s);
+
+// Ingest and orientation (kc_graph.hip)
+kc_status kc_canonicalise(kc_graph *g, const uint32_t *d_src, const uint32_t *d_dst);
+kc_status kc_orient_impl(kc_graph *g);
+
+// Counting (kc_count.hip)
+struct kc_count_args {
+    int k = 3;
+    int colored = 0;
+    uint32_t c = 1;
+    uint64_t seed = 0;
+    int scheme = KC_COLOR_PER_ROOT;
+    uint64_t *per_root = nullptr;  // device [n] by original id, optional
+    int policy = KC_SCHED_DEGREE;
+};
+kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *total, int *overflow);
+
+// Scheduler (kc_sched.hip)
+#define KC_MLP_IN 8
+#define KC_MLP_H 32
+#define KC_MLP_PARAMS (KC_MLP_IN * KC_MLP_H + KC_MLP_H + KC_MLP_H * KC_MLP_H + KC_MLP_H + KC_MLP_H + 1)
+struct kc_queue {
+    kc_tmp buf;          // root ranks, tiers concatenated
+    uint32_t count[4];   // roots per tier: wave, workgroup, scratch, (unused)
+    uint32_t offset[4];
+    uint32_t max_d[4];   // largest out-degree in each tier
+};
+kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_max, kc_queue &q);
+kc_status kc_features(const kc_graph *g, float *d_feat, hipStream_t s);
+
+// ----------------------------------------------------------------------------
+// Wave64 helpers
+#ifdef __HIP_DEVICE_COMPILE__
+#define KC_DEV __device__ __forceinline__
+#else
+#define KC_DEV __device__ inline
+#endif
+
+KC_DEV uint32_t kc_lane() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+KC_DEV uint64_t kc_lanemask_lt() { return (1ull << kc_lane()) - 1ull; }
+
+// SplitMix64 finaliser (Steele, Lea & Flood 2014)
+__host__ __device__ inline uint64_t kc_mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+__host__ __device__ inline uint32_t kc_colour(uint64_t h, uint32_t c) {
+    return (uint32_t)(((h >> 32) * (uint64_t)c) >> 32);
+}
+
+KC_DEV uint64_t kc_wave_sum_u64(uint64_t v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+KC_DEV uint32_t kc_wave_sum_u32(uint32_t v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+KC_DEV uint32_t kc_wave_max_u32(uint32_t v) {
+    for (int off = 32; off >= 1; off >>= 1) {
+        uint32_t o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+// Exact wave-wide sum of 64-bit values; sets *ovf if the sum needs more than 64 bits.
+KC_DEV uint64_t kc_wave_sum_checked(uint64_t v, int *ovf) {
+    uint64_t lo = kc_wave_sum_u64(v & 0xffffffffull);
+    uint64_t hi = kc_wave_sum_u64(v >> 32);
+    if (hi >> 32) *ovf = 1;
+    uint64_t t = hi << 32, r = t + lo;
+    if (r < t) *ovf = 1;
+    return r;
+}
+// inclusive prefix sum across the wave
+KC_DEV uint32_t kc_wave_incl_u32(uint32_t v) {
+    const uint32_t lane = kc_lane();
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t o = __shfl_up(v, off, 64);
+        if (lane >= (uint32_t)off) v += o;
+    }
+    return v;
+}

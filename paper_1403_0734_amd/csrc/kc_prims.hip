@@ -1,0 +1,195 @@
+// Device-wide primitives: exclusive scan and a stable LSD radix sort of 64-bit
+// keys.  Both are HBM-bound passes used by canonicalisation, orientation and
+// queue building.
+#include "kc_internal.h"
+
+namespace {
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+// Block-wide exclusive scan of one value per thread; returns the block total.
+template <typename T>
+__device__ T block_excl_scan(T v, T *s_waves, T &total) {
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    T x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        T o = __shfl_up(x, off, 64);
+        if (lane >= off) x += o;
+    }
+    if (lane == 63) s_waves[wave] = x;
+    __syncthreads();
+    T wbase = 0, tot = 0;
+    for (int w = 0; w < SCAN_THREADS / 64; ++w) {
+        if (w < wave) wbase += s_waves[w];
+        tot += s_waves[w];
+    }
+    total = tot;
+    __syncthreads();
+    return wbase + x - v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_reduce(const T *in, size_t n, T *partial) {
+    __shared__ T s_waves[SCAN_THREADS / 64];
+    const size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j)
+        if (base + j < n) s += in[base + j];
+    T total;
+    (void)block_excl_scan<T>(s, s_waves, total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+// Exclusive scan of each tile, offset by the scanned tile partials (may be null).
+template <typename T>
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_apply(const T *in, T *out, size_t n, const T *partial_excl,
+                                                             T *d_total) {
+    __shared__ T s_waves[SCAN_THREADS / 64];
+    const size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
+    T v[SCAN_ITEMS];
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        v[j] = (base + j < n) ? in[base + j] : (T)0;
+        s += v[j];
+    }
+    T total;
+    T run = block_excl_scan<T>(s, s_waves, total);
+    if (partial_excl) run += partial_excl[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        if (base + j < n) out[base + j] = run;
+        run += v[j];
+    }
+    if (d_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_THREADS - 1) *d_total = run;
+}
+
+template <typename T>
+kc_status scan_excl(const T *in, T *out, size_t n, T *d_total, hipStream_t s) {
+    if (n == 0) {
+        if (d_total) KC_HIP(hipMemsetAsync(d_total, 0, sizeof(T), s));
+        return KC_OK;
+    }
+    const size_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (tiles == 1) {
+        hipLaunchKernelGGL(k_scan_apply<T>, dim3(1), dim3(SCAN_THREADS), 0, s, in, out, n, (const T *)nullptr,
+                           d_total);
+        KC_HIP(hipGetLastError());
+        return KC_OK;
+    }
+    kc_tmp part, part_x;
+    KC_TRY(kc_tmp_alloc(part, tiles * sizeof(T), s));
+    KC_TRY(kc_tmp_alloc(part_x, tiles * sizeof(T), s));
+    hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, s, in, n, part.as<T>());
+    KC_HIP(hipGetLastError());
+    KC_TRY(scan_excl<T>(part.as<T>(), part_x.as<T>(), tiles, (T *)nullptr, s));
+    hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, s, in, out, n,
+                       (const T *)part_x.as<T>(), d_total);
+    KC_HIP(hipGetLastError());
+    return KC_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Radix sort: 8-bit digits, 256 threads x 16 keys per tile.  Per pass:
+// tile histograms (digit-major), one exclusive scan, stable scatter.
+constexpr int RS_THREADS = 256;
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+
+// Lanes whose 8-bit digit equals this lane's (among valid lanes).
+__device__ __forceinline__ uint64_t match_digit8(uint32_t d, bool valid) {
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+    }
+    return valid ? peers : 0ull;
+}
+
+__global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const uint64_t *keys, size_t n, int shift, uint32_t *hist,
+                                                        uint32_t nblocks) {
+    __shared__ uint32_t s_h[256];
+    s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const size_t base = (size_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const size_t i = base + (size_t)r * RS_THREADS + threadIdx.x;
+        const bool valid = i < n;
+        const uint32_t d = valid ? (uint32_t)(keys[i] >> shift) & 255u : 0u;
+        const uint64_t peers = match_digit8(d, valid);
+        if (valid && (peers & kc_lanemask_lt()) == 0) atomicAdd(&s_h[d], (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = s_h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint64_t *in, uint64_t *out, size_t n, int shift,
+                                                           const uint32_t *offs, uint32_t nblocks) {
+    __shared__ uint32_t s_base[256];
+    __shared__ uint32_t s_w[RS_THREADS / 64][256];
+    const int tid = threadIdx.x, wave = tid >> 6;
+    s_base[tid] = offs[(size_t)tid * nblocks + blockIdx.x];
+    const size_t base = (size_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const size_t i = base + (size_t)r * RS_THREADS + tid;
+        const bool valid = i < n;
+        const uint64_t key = valid ? in[i] : 0ull;
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+#pragma unroll
+        for (int w = 0; w < RS_THREADS / 64; ++w) s_w[w][tid] = 0;
+        __syncthreads();
+        const uint64_t peers = match_digit8(d, valid);
+        const uint64_t lower = peers & kc_lanemask_lt();
+        if (valid && lower == 0) s_w[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t off = s_base[d] + (uint32_t)__popcll(lower);
+            for (int w = 0; w < wave; ++w) off += s_w[w][d];
+            out[off] = key;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < RS_THREADS / 64; ++w) add += s_w[w][tid];
+        s_base[tid] += add;
+    }
+}
+
+}  // namespace
+
+kc_status kc_scan_excl_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *d_total, hipStream_t s) {
+    return scan_excl<uint32_t>(in, out, n, d_total, s);
+}
+kc_status kc_scan_excl_u64(const uint64_t *in, uint64_t *out, size_t n, uint64_t *d_total, hipStream_t s) {
+    return scan_excl<uint64_t>(in, out, n, d_total, s);
+}
+
+kc_status kc_radix_sort_u64(uint64_t *keys, uint64_t *tmp, size_t n, int bit_lo, int bit_hi, hipStream_t s) {
+    if (n <= 1 || bit_hi <= bit_lo) return KC_OK;
+    if (n >= (1ull << 32)) return kc_fail(KC_EINVAL, "radix sort of %zu keys exceeds 2^32", n);
+    const uint32_t nblocks = (uint32_t)((n + RS_TILE - 1) / RS_TILE);
+    kc_tmp hist, offs;
+    KC_TRY(kc_tmp_alloc(hist, (size_t)256 * nblocks * sizeof(uint32_t), s));
+    KC_TRY(kc_tmp_alloc(offs, (size_t)256 * nblocks * sizeof(uint32_t), s));
+    uint64_t *src = keys, *dst = tmp;
+    int passes = 0;
+    for (int shift = bit_lo; shift < bit_hi; shift += 8, ++passes) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(RS_THREADS), 0, s, (const uint64_t *)src, n, shift,
+                           hist.as<uint32_t>(), nblocks);
+        KC_HIP(hipGetLastError());
+        KC_TRY(kc_scan_excl_u32(hist.as<uint32_t>(), offs.as<uint32_t>(), (size_t)256 * nblocks, nullptr, s));
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(RS_THREADS), 0, s, (const uint64_t *)src, dst, n,
+                           shift, (const uint32_t *)offs.as<uint32_t>(), nblocks);
+        KC_HIP(hipGetLastError());
+        uint64_t *t = src;
+        src = dst;
+        dst = t;
+    }
+    if (passes & 1) KC_HIP(hipMemcpyAsync(keys, tmp, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    return KC_OK;
+}

@@ -1,0 +1,224 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element by
+element and bit-exact (all results are integers).  Sizes span several tiles and
+every tier: wave (out-degree <= 64), workgroup (LDS bitmap) and scratch (global
+bitmap), with ragged tails and the degenerate cases."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import graphgen as G
+from graphgen import small as S
+from paper_1403_0734_amd import kc as K
+
+from gpu_util import announce, csr, device_graph, oriented, per_root
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [
+    S.complete(5), S.complete(66), S.complete(130), S.complete_multipartite([3, 1, 4, 1, 5, 9, 2, 6]),
+    S.turan(40, 7), S.cycle(9), S.star(70), S.empty(7), S.path(12),
+    S.random_graph(60, 0.5, 1, dup_frac=0.3, loops=5),
+    S.random_graph(150, 0.6, 2), S.random_graph(300, 0.3, 3, dup_frac=0.1, loops=2),
+    S.planted_small(400, 0.02, [list(range(0, 60, 2)), list(range(100, 190, 3)), list(range(5, 395, 5))], 4),
+    S.disjoint_union(S.complete(20), S.complete_multipartite([4, 4, 4, 4]), S.random_graph(90, 0.4, 5)),
+]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    K.load()
+
+
+def _close(h):
+    K.kc_graph_destroy(h)
+
+
+def bounded_ks(og, lo=1, hi=K.KC_KMAX, budget=2e7):
+    """Clique sizes whose enumeration stays cheap: stop after the first k whose
+    (k-1)-clique count exceeds the budget (both sides enumerate them)."""
+    out = []
+    for k in range(lo, hi + 1):
+        if k >= 4 and og.count(k - 1) > budget:
+            break
+        out.append(k)
+    return out
+
+
+@pytest.mark.parametrize("el", SMALL, ids=lambda e: e.name[:40])
+def test_csr_and_orientation_match_oracle(el):
+    announce(f"csr/orientation {el.name}")
+    og = O.OracleGraph.from_edgelist(el)
+    h = device_graph(el)
+    n, m, dmax = K.kc_graph_info(h)
+    assert (n, m) == (og.n, og.m)
+    assert dmax == og.max_outdeg()
+    # symmetric CSR of the simple graph and degrees
+    rp, col, deg = csr(h, n, m)
+    eu, ev = og.canon_edges()
+    pairs = np.concatenate([np.stack([eu, ev], 1), np.stack([ev, eu], 1)]).astype(np.uint64)
+    order = np.lexsort((pairs[:, 1], pairs[:, 0]))
+    pairs = pairs[order]
+    want_rp = np.zeros(n + 1, np.uint64)
+    np.add.at(want_rp, pairs[:, 0].astype(np.int64) + 1, 1)
+    want_rp = np.cumsum(want_rp).astype(np.uint64)
+    assert np.array_equal(rp, want_rp)
+    assert np.array_equal(col, pairs[:, 1].astype(np.uint32))
+    assert np.array_equal(deg, og.degrees())
+    # oriented CSR in rank space, byte for byte
+    optr, ocol, r2i = oriented(h, n, m)
+    w_optr, w_ocol = og.rank_csr()
+    assert np.array_equal(r2i, og.rank2id())
+    assert np.array_equal(optr, w_optr)
+    assert np.array_equal(ocol, w_ocol)
+    _close(h)
+
+
+@pytest.mark.parametrize("el", SMALL, ids=lambda e: e.name[:40])
+def test_exact_counts_small(el):
+    og = O.OracleGraph.from_edgelist(el)
+    h = device_graph(el)
+    for k in bounded_ks(og):
+        announce(f"count {el.name} k={k}")
+        assert K.kc_count(h, k) == og.count(k), (el.name, k)
+    _close(h)
+
+
+@pytest.mark.parametrize("el", SMALL[:9] + SMALL[10:13], ids=lambda e: e.name[:40])
+def test_per_root_counts_and_work(el):
+    og = O.OracleGraph.from_edgelist(el)
+    h = device_graph(el)
+    for k in [k for k in bounded_ks(og, 3, 7) if k in (3, 4, 5, 7)]:
+        announce(f"per-root {el.name} k={k}")
+        c, w = per_root(h, el.n, k, with_work=True)
+        assert np.array_equal(c, og.count_per_root(k)), (el.name, k)
+        inter, _ = og.work_per_root(k)
+        assert np.array_equal(w, inter), (el.name, k)
+    _close(h)
+
+
+def test_tier_boundaries_complete_graphs():
+    """K_n has out-degrees 0..n-1, so one graph crosses every tier threshold; the
+    closed form C(n, k) is the reference (no oracle run needed at this size)."""
+    for n, ks in [(40, range(3, 11)), (63, range(3, 7)), (64, range(3, 7)), (65, range(3, 7)),
+                  (129, range(3, 6)), (700, [3, 4]), (1300, [3, 4])]:
+        h = device_graph(S.complete(n))
+        for k in ks:
+            announce(f"K{n} k={k}")
+            assert K.kc_count(h, k) == math.comb(n, k), (n, k)
+        _close(h)
+
+
+def test_complete_multipartite_large():
+    parts = [200, 150, 300, 90, 310]  # wide roots on every tier; e_4 ~ 1e10 cliques
+    h = device_graph(S.complete_multipartite(parts))
+    poly = [1]
+    for a in parts:
+        nxt = poly + [0]
+        for i in range(len(poly)):
+            nxt[i + 1] += poly[i] * a
+        poly = nxt
+    for k in range(3, 5):
+        announce(f"multipartite k={k}")
+        assert K.kc_count(h, k) == poly[k]
+    _close(h)
+
+
+@pytest.mark.parametrize("scheme", [K.KC_COLOR_PER_ROOT, K.KC_COLOR_GLOBAL])
+def test_colour_raw_counts_match_oracle(scheme):
+    for el in [SMALL[1], SMALL[2], SMALL[10], SMALL[11], SMALL[12]]:
+        og = O.OracleGraph.from_edgelist(el)
+        h = device_graph(el)
+        for k in bounded_ks(og, 3, 6, budget=5e6):
+            for c in [1, 2, 3, 8]:
+                for seed in [11, 2**63 + 5]:
+                    announce(f"colour {el.name} k={k} c={c} scheme={scheme}")
+                    e = K.kc_count_colored(h, k, c, seed, scheme)
+                    raw = og.count_colored(k, c, seed, scheme)
+                    assert e.raw == raw, (el.name, k, c, seed, scheme)
+                    exp = k - 2 if scheme == K.KC_COLOR_PER_ROOT else k - 1
+                    assert e.scale_exponent == exp
+                    assert e.estimate == float(raw * c ** exp)
+                    assert bool(e.estimate_fits_u64) == (raw * c ** exp < 2**64)
+                    if e.estimate_fits_u64:
+                        assert e.estimate_u64 == raw * c ** exp
+        _close(h)
+
+
+def test_repeat_runs_identical():
+    el = SMALL[12]
+    h = device_graph(el)
+    for k in [4, 6]:
+        vals = {K.kc_count(h, k) for _ in range(3)}
+        assert len(vals) == 1
+    _close(h)
+
+
+def test_host_input_path():
+    el = SMALL[10]
+    og = O.OracleGraph.from_edgelist(el)
+    h = K.kc_graph_create(el.src, el.dst, el.m_in, el.n, False, None)
+    K.kc_orient(h)
+    K.kc_orient(h)  # idempotent
+    for k in [3, 4, 5]:
+        assert K.kc_count(h, k) == og.count(k)
+    _close(h)
+
+
+def test_error_paths():
+    el = S.complete(6)
+    h = device_graph(el, orient=False)
+    with pytest.raises(K.KcError) as e:
+        K.kc_count(h, 3)
+    assert e.value.status == K.KC_ESTATE
+    K.kc_orient(h)
+    for bad_k in [0, -1, K.KC_KMAX + 1]:
+        with pytest.raises(K.KcError) as e:
+            K.kc_count(h, bad_k)
+        assert e.value.status == K.KC_EINVAL
+    with pytest.raises(K.KcError) as e:
+        K.kc_count_colored(h, 3, 0, 1)
+    assert e.value.status == K.KC_EINVAL
+    with pytest.raises(K.KcError) as e:
+        K.kc_count_colored(h, 3, 2, 1, 7)
+    assert e.value.status == K.KC_EINVAL
+    _close(h)
+    bad = np.array([0, 1, 9], np.uint32)
+    with pytest.raises(K.KcError) as e:
+        K.kc_graph_create(bad, np.array([1, 2, 3], np.uint32), 3, 5, False, None)
+    assert e.value.status == K.KC_EINVAL
+    with pytest.raises(K.KcError) as e:
+        K.kc_graph_create(None, None, 3, 5, False, None)
+    assert e.value.status == K.KC_EINVAL
+
+
+def test_overflow_is_reported(monkeypatch):
+    """The carry check of the global sum, forced from the host: the total starts
+    at 2^64 - 5, so adding the 10 triangles of K_5 must report KC_EOVERFLOW."""
+    h = device_graph(S.complete(5))
+    monkeypatch.setenv("KC_TEST_TOTAL_BIAS", str(2**64 - 5))
+    with pytest.raises(K.KcError) as e:
+        K.kc_count(h, 3)
+    assert e.value.status == K.KC_EOVERFLOW
+    monkeypatch.setenv("KC_TEST_TOTAL_BIAS", str(2**64 - 11))
+    assert K.kc_count(h, 3) == 2**64 - 1
+    monkeypatch.delenv("KC_TEST_TOTAL_BIAS")
+    assert K.kc_count(h, 3) == 10
+    _close(h)
+
+
+def test_er2000_workload_against_golden():
+    import json, os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "counts.json")))["er2000"]
+    el = G.workload_er2000()
+    assert el.digest() == gold["digest"]
+    h = device_graph(el)
+    for k, q in gold["q"].items():
+        assert K.kc_count(h, int(k)) == q
+    for rec in gold["colour"]:
+        e = K.kc_count_colored(h, rec["k"], rec["c"], rec["seed"], rec["scheme"])
+        assert e.raw == rec["raw"]
+    _close(h)
