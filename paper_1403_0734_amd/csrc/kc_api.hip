@@ -59,6 +59,22 @@ kc_status kc_tmp_alloc(kc_tmp &t, size_t bytes, hipStream_t s) {
     return KC_OK;
 }
 
+kc_status kc_dev_alloc(void **p, size_t bytes, hipStream_t s) {
+    kc_tmp t;
+    KC_TRY(kc_tmp_alloc(t, bytes, s));
+    *p = t.p;
+    t.p = nullptr;  // ownership moves to the caller
+    return KC_OK;
+}
+
+uint64_t *kc_pinned_scratch() {
+    static thread_local uint64_t *buf = nullptr;
+    if (!buf) {
+        if (hipHostMalloc((void **)&buf, 512, hipHostMallocDefault) != hipSuccess) buf = nullptr;
+    }
+    return buf;
+}
+
 extern "C" {
 
 const char *kc_status_str(kc_status s) {
@@ -79,12 +95,11 @@ const char *kc_status_str(kc_status s) {
 
 void kc_graph_destroy(kc_graph *g) {
     if (!g) return;
-    if (g->stream) (void)hipStreamSynchronize(g->stream);
-    else (void)hipDeviceSynchronize();
-    void *bufs[] = {g->rowptr, g->col, g->deg, g->ukeys, g->optr, g->ocol, g->rank2id, g->id2rank, g->mlp, g->d_res};
+    void *bufs[] = {g->rowptr, g->col, g->deg, g->ukeys, g->optr, g->ocol, g->rank2id, g->id2rank, g->mlp, g->d_res, g->dq};
     for (void *b : bufs)
-        if (b) (void)hipFree(b);
-    if (g->h_res) (void)hipHostFree(g->h_res);
+        if (b) (void)hipFreeAsync(b, g->stream);
+    (void)hipStreamSynchronize(g->stream);
+    delete[] g->dq_hist;
     for (hipEvent_t e : g->ev)
         if (e) (void)hipEventDestroy(e);
     delete g;
@@ -98,8 +113,8 @@ static kc_status create_impl(const uint32_t *src, const uint32_t *dst, uint64_t 
     g->m_in = m_in;
     g->idbits = bits_for(n);
     for (auto &e : g->ev) KC_HIP(hipEventCreate(&e));
-    KC_HIP(hipMalloc(&g->d_res, 64 * sizeof(uint64_t)));
-    KC_HIP(hipHostMalloc(&g->h_res, 64 * sizeof(uint64_t), hipHostMallocDefault));
+    KC_TRY(kc_dev_alloc((void **)&g->d_res, 64 * sizeof(uint64_t), g->stream));
+    if (!kc_pinned_scratch()) return kc_fail(KC_ENOMEM, "pinned host buffer");
     const uint32_t *ds = src, *dd = dst;
     kc_tmp cs, cd;
     if (!src_on_device && m_in) {

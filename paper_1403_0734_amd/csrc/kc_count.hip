@@ -18,18 +18,19 @@
 //            Gamma+(u) is first cut to the nodes that share u's colour.
 //
 // Tiers (by out-degree d = |Gamma+(u)|):
-//   wave       d <= 64: one wave per root, one 64-bit row per node held in LDS;
-//              the count runs as a per-lane depth-first state machine over the
-//              edges (i, j) of G+(u), refilling lanes from a wave-local queue.
+//   wave       d <= 64: one wave per root; G+(u) is a local graph of one 64-bit
+//              row per node, counted by the lane state machine below.
 //   workgroup  64 < d <= D_LDS: one workgroup per root, packed upper-triangular
-//              bitmap in LDS; waves take first-level nodes, lanes span words.
+//              bitmap in LDS.  Waves take first-level nodes v; a candidate set
+//              of at most 64 nodes is compacted into a local graph and counted
+//              like a wave-tier root, larger ones are split one level further.
 //   scratch    d > D_LDS: as workgroup, bitmap in a global-memory slice.
 // Every count is an exact uint64; sums are carry-checked.
 #include "kc_internal.h"
 
 namespace {
 
-constexpr int WG = 256;            // threads per block in every count kernel
+constexpr int WG = 256;  // threads per block in every count kernel
 constexpr int WAVES = WG / 64;
 
 // ----------------------------------------------------------------------------
@@ -56,8 +57,7 @@ __device__ __forceinline__ uint32_t select_bit(uint64_t w, uint32_t r) {
 }
 
 // largest i in [0, d) with seg[i] <= e  (seg[0] = 0 <= e)
-template <typename P>
-__device__ __forceinline__ uint32_t seg_find(const P *seg, uint32_t d, uint32_t e) {
+__device__ __forceinline__ uint32_t seg_find(const uint32_t *seg, uint32_t d, uint32_t e) {
     uint32_t lo = 0, hi = d;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
@@ -87,20 +87,19 @@ struct CountParams {
     const uint64_t *optr;
     const uint32_t *ocol;
     const uint32_t *rank2id;
-    const uint32_t *queue;     // root ranks of this tier
-    uint32_t count;            // roots in the queue
-    uint32_t *next;            // dynamic queue cursor (zeroed before launch)
-    uint64_t *per_root;        // optional, by original id
-    unsigned long long *total; // global sum
-    uint32_t *overflow;        // set when a sum does not fit in 64 bits
+    const uint32_t *queue;      // root ranks of this tier
+    uint32_t count;             // roots in the queue
+    uint32_t *next;             // dynamic queue cursor (zeroed before launch)
+    uint64_t *per_root;         // optional, by original id
+    unsigned long long *total;  // global sum
+    uint32_t *overflow;         // set when a sum does not fit in 64 bits
     int colored;
     int scheme;
     uint32_t c;
     uint64_t seed;
-    // scratch tier
-    uint64_t *gscratch;        // per-block slices
-    size_t slice_words;        // u64 words per block slice
-    uint32_t dcap;             // largest d the slice/LDS layout holds
+    uint64_t *gscratch;   // scratch tier: per-block slices
+    size_t slice_words;   // u64 words per slice
+    uint32_t dcap;        // largest d the workgroup layout holds
 };
 
 __device__ __forceinline__ void add_total(const CountParams &p, uint64_t v, int ovf) {
@@ -110,41 +109,162 @@ __device__ __forceinline__ void add_total(const CountParams &p, uint64_t v, int 
     if (old + v < old) atomicOr(p.overflow, 1u);
 }
 
+// Roots per queue fetch: one device-scope atomic serves a chunk of roots.
+__device__ __forceinline__ uint32_t queue_chunk(uint32_t count, uint32_t workers) {
+    const uint32_t c = count / (workers * 8u);
+    return c < 1u ? 1u : (c > 64u ? 64u : c);
+}
+
 // ============================================================================
-// Wave tier: d <= 64
+// Local graphs of at most 64 nodes: one 64-bit upper-triangular row per node.
+// local_count adds the number of ell-cliques of such a graph to the lanes' acc.
+// For ell >= 3 the cliques are enumerated below the edges (i, j) of the local
+// graph: every lane runs its own depth-first state machine over one edge's
+// candidate set P = row_i & row_j and takes a new edge when it is done, so lanes
+// do not wait for each other's subtrees.
+// Rows of lanes >= s must be zero.
 // ============================================================================
-template <int K>
-struct WaveSmem {
-    uint32_t nb[64];
-    uint32_t seg[64];
-    uint32_t epre[64];
-    uint32_t colr[64];
-    uint64_t delta[64];
+struct LocalArea {
     uint64_t rows[64];
-    uint64_t stk[(K > 4 ? K - 4 : 1)][64];
-    uint32_t task_next;
+    uint32_t epre[64];
+    uint32_t members[64];
+    uint64_t stk[KC_KMAX - 4][64];
+};
+
+__device__ __forceinline__ void local_count(LocalArea &A, uint32_t s, int ell, uint64_t &acc) {
+    const uint32_t lane = kc_lane();
+    const uint64_t row = A.rows[lane];
+    if (ell <= 1) {
+        if (lane == 0) acc += ell == 1 ? s : 1u;
+        return;
+    }
+    if (ell == 2) {
+        acc += (uint64_t)__popcll(row);
+        return;
+    }
+    const int R = ell - 2;  // nodes to choose inside an edge's candidate set
+    const uint32_t ce = (uint32_t)__popcll(row);
+    const uint32_t ei = kc_wave_incl_u32(ce);
+    const uint32_t E = __shfl(ei, 63, 64);
+    A.epre[lane] = ei - ce;
+    wave_sync();
+    // Idle lanes are refilled together, once at least REFILL of them wait (or
+    // no lane is busy): task t of the i-th idle lane is next + i.
+    constexpr uint32_t REFILL = 16;
+    int depth = -1;
+    uint32_t next = 0;
+    for (;;) {
+        const uint64_t idle = __ballot(depth < 0);
+        const uint32_t nidle = (uint32_t)__popcll(idle);
+        if (next < E && (nidle >= REFILL || nidle == 64)) {
+            const uint32_t t = next + (uint32_t)__popcll(idle & kc_lanemask_lt());
+            next += nidle;
+            if (depth < 0 && t < E) {
+                const uint32_t i = seg_find(A.epre, s, t);
+                const uint64_t ri = A.rows[i];
+                const uint32_t j = select_bit(ri, t - A.epre[i]);
+                const uint64_t P = ri & A.rows[j];
+                if (R == 1) {
+                    acc += (uint64_t)__popcll(P);
+                } else if ((int)__popcll(P) >= R) {
+                    depth = 0;
+                    A.stk[0][lane] = P;
+                }
+            }
+        } else if (nidle == 64) {
+            break;
+        }
+        if (depth >= 0) {
+            uint64_t cur = A.stk[depth][lane];
+            if (cur == 0) {
+                --depth;
+            } else {
+                const uint32_t v = (uint32_t)__builtin_ctzll(cur);
+                cur &= cur - 1;
+                A.stk[depth][lane] = cur;
+                const uint64_t child = cur & A.rows[v];
+                const int rem = R - depth - 1;  // nodes still to choose after v
+                if (rem == 1) {
+                    acc += (uint64_t)__popcll(child);
+                } else if ((int)__popcll(child) >= rem) {
+                    ++depth;
+                    A.stk[depth][lane] = child;
+                }
+            }
+        }
+    }
+    wave_sync();
+}
+
+// ============================================================================
+// Wave tier: d <= 64.  Consecutive roots of the queue whose out-degrees sum to
+// at most 64 share one wave pass: their G+(u) are laid side by side as the
+// diagonal blocks of one 64-node local graph (no edge joins two blocks, so its
+// cliques are exactly the union of the roots' cliques).  When per-root counts
+// are requested, or with the global colouring (which cuts Gamma+(u) first),
+// every pass holds one root.
+// ============================================================================
+struct WaveSmem {
+    LocalArea A;
+    uint32_t nb[64];      // the packed Gamma+ lists
+    uint32_t seg[64];     // exclusive prefix of their out-degrees
+    uint32_t colr[64];
+    uint32_t rstart[64];  // first lane of each packed root
+    uint8_t blo[64], bhi[64];  // block [blo, bhi) of each lane
+    uint64_t delta[64];
 };
 
 template <int K>
 __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
-    __shared__ WaveSmem<K> sm_all[WAVES];
+    __shared__ WaveSmem sm_all[WAVES];
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    WaveSmem<K> &sm = sm_all[wave];
-    constexpr int R = K - 3;  // nodes to choose below an edge task
-    uint64_t wave_total = 0;
+    WaveSmem &sm = sm_all[wave];
+    const uint32_t chunk = queue_chunk(p.count, gridDim.x * WAVES);
+    const bool single = p.per_root != nullptr || (p.colored && p.scheme == KC_COLOR_GLOBAL);
+    uint64_t wave_total = 0, acc = 0;
     int ovf = 0;
+    uint32_t cb = 0, cn = 0, ci = 0;  // chunk start, size, next unpacked root
+    uint32_t my_u = 0, my_d = 0;      // lane t holds root t of the chunk
+    uint64_t my_base = 0;
 
     for (;;) {
-        uint32_t qi = 0;
-        if (lane == 0) qi = atomicAdd(p.next, 1u);
-        qi = __shfl(qi, 0, 64);
-        if (qi >= p.count) break;
-        const uint32_t u = p.queue[qi];
-        const uint64_t base = p.optr[u];
-        uint32_t d = (uint32_t)(p.optr[u + 1] - base);
+        if (ci >= cn) {
+            uint32_t b = 0;
+            if (lane == 0) b = atomicAdd(p.next, chunk);
+            b = __shfl(b, 0, 64);
+            if (b >= p.count) break;
+            cb = b;
+            cn = (p.count - b) < chunk ? (p.count - b) : chunk;
+            ci = 0;
+            my_d = 0;
+            if (lane < cn) {
+                my_u = p.queue[cb + lane];
+                my_base = p.optr[my_u];
+                my_d = (uint32_t)(p.optr[my_u + 1] - my_base);
+            }
+        }
+        // pack roots ci, ci+1, ... while their out-degrees sum to at most 64
+        const bool cand = lane >= ci && lane < cn;
+        const uint32_t dl = cand ? my_d : 0u;
+        const uint32_t incl = kc_wave_incl_u32(dl);
+        const uint32_t before = __shfl(incl - dl, ci, 64);  // sum below root ci
+        uint32_t g = (uint32_t)__popcll(__ballot(cand && incl - before <= 64u));
+        if (single || g == 0) g = 1;
+        const uint32_t S = __shfl(incl, ci + g - 1, 64) - before;  // lanes used
+        if (lane >= ci && lane < ci + g) sm.rstart[lane - ci] = incl - dl - before;
+        wave_sync();
+        uint32_t r = 0;  // packed root of this lane
+        if (lane < S) r = seg_find(sm.rstart, g, lane);
+        const uint32_t rl = ci + r;
+        const uint32_t u = __shfl(my_u, rl, 64);
+        const uint64_t rbase = __shfl(my_base, rl, 64);
+        const uint32_t rd = __shfl(my_d, rl, 64);
+        const uint32_t r0 = lane < S ? sm.rstart[r] : 0u;
+        ci += g;
+        uint32_t d = S;
 
-        // Gamma+(u) into LDS; optionally cut to u's colour (global scheme)
-        uint32_t a = lane < d ? p.ocol[base + lane] : 0xFFFFFFFFu;
+        // Gamma+ lists into LDS; optionally cut to u's colour (global scheme, one root)
+        uint32_t a = lane < S ? p.ocol[rbase + (lane - r0)] : 0xFFFFFFFFu;
         if (p.colored && p.scheme == KC_COLOR_GLOBAL) {
             const uint32_t cu = node_colour(p.seed, p.rank2id[u], p.c);
             const bool keep = lane < d && node_colour(p.seed, p.rank2id[a], p.c) == cu;
@@ -158,103 +278,59 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
             a = sm.nb[lane];
         }
         sm.nb[lane] = a;
+        sm.blo[lane] = (uint8_t)(lane < d ? r0 : 0u);
+        sm.bhi[lane] = (uint8_t)(lane < d ? (single ? d : r0 + rd) : 0u);
         uint32_t len = 0;
         uint64_t ob = 0;
         if (lane < d) {
             ob = p.optr[a];
             len = (uint32_t)(p.optr[a + 1] - ob);
         }
-        const uint32_t incl = kc_wave_incl_u32(len);
-        const uint32_t excl = incl - len;
-        const uint32_t Ttot = __shfl(incl, 63, 64);
+        const uint32_t sincl = kc_wave_incl_u32(len);
+        const uint32_t excl = sincl - len;
+        const uint32_t Ttot = __shfl(sincl, 63, 64);
         sm.seg[lane] = excl;
         sm.delta[lane] = ob - excl;
-        sm.rows[lane] = 0;
+        sm.A.rows[lane] = 0;
         if (p.colored && p.scheme == KC_COLOR_PER_ROOT)
             sm.colr[lane] = lane < d ? root_colour(p.seed, p.rank2id[u], p.rank2id[a], p.c) : 0u;
         wave_sync();
 
-        // staging: row i bit j = [a_j in Gamma+(a_i)]
+        // staging: row i bit j = [a_j in Gamma+(a_i)], j inside i's block
         if (d > 0) {
-            const uint32_t alast = sm.nb[d - 1];
             for (uint32_t e = lane; e < Ttot; e += 64) {
                 const uint32_t i = seg_find(sm.seg, d, e);
                 const uint32_t y = p.ocol[sm.delta[i] + e];
-                if (y > alast) continue;
-                const uint32_t j = lower_bound_u32(sm.nb, d, y);
+                const uint32_t lo = sm.blo[i], hi = sm.bhi[i];
+                if (y > sm.nb[hi - 1]) continue;
+                const uint32_t j = lo + lower_bound_u32(sm.nb + lo, hi - lo, y);
                 if (sm.nb[j] != y) continue;
                 if (p.colored && p.scheme == KC_COLOR_PER_ROOT && sm.colr[i] != sm.colr[j]) continue;
-                atomicOr((unsigned long long *)&sm.rows[i], 1ull << j);
+                atomicOr((unsigned long long *)&sm.A.rows[i], 1ull << j);
             }
         }
         wave_sync();
-        const uint64_t myrow = sm.rows[lane];
+        local_count(sm.A, d, K - 1, acc);
 
-        uint64_t acc = 0;
-        if constexpr (K == 3) {
-            acc = (uint64_t)__popcll(myrow);
-        } else {
-            // edge tasks (i, j), j in row_i, enumerated through a prefix of row popcounts
-            const uint32_t ce = (uint32_t)__popcll(myrow);
-            const uint32_t ei = kc_wave_incl_u32(ce);
-            const uint32_t E = __shfl(ei, 63, 64);
-            sm.epre[lane] = ei - ce;
-            if (lane == 0) sm.task_next = 0;
-            wave_sync();
-            int depth = -1;
-            bool more = true;
-            for (;;) {
-                if (depth < 0 && more) {
-                    const uint32_t t = atomicAdd(&sm.task_next, 1u);
-                    if (t >= E) {
-                        more = false;
-                    } else {
-                        const uint32_t i = seg_find(sm.epre, d, t);
-                        const uint64_t ri = sm.rows[i];
-                        const uint32_t j = select_bit(ri, t - sm.epre[i]);
-                        const uint64_t P = ri & sm.rows[j];
-                        if constexpr (R == 1) {
-                            acc += (uint64_t)__popcll(P);
-                        } else {
-                            if ((uint32_t)__popcll(P) >= (uint32_t)R) {
-                                depth = 0;
-                                sm.stk[0][lane] = P;
-                            }
-                        }
-                    }
-                } else if (depth >= 0) {
-                    if constexpr (R >= 2) {
-                        uint64_t cur = sm.stk[depth][lane];
-                        if (cur == 0) {
-                            --depth;
-                        } else {
-                            const uint32_t v = (uint32_t)__builtin_ctzll(cur);
-                            cur &= cur - 1;
-                            sm.stk[depth][lane] = cur;
-                            const uint64_t child = cur & sm.rows[v];
-                            const int rem = R - depth - 1;  // nodes still to choose after v
-                            if (rem == 1) {
-                                acc += (uint64_t)__popcll(child);
-                            } else if ((int)__popcll(child) >= rem) {
-                                ++depth;
-                                sm.stk[depth][lane] = child;
-                            }
-                        }
-                    }
-                }
-                if (!__any(depth >= 0 || more)) break;
+        if (p.per_root) {
+            const uint64_t q = kc_wave_sum_checked(acc, &ovf);
+            acc = 0;
+            if (lane == 0) {
+                p.per_root[p.rank2id[u]] = q;
+                const uint64_t nt = wave_total + q;
+                if (nt < wave_total) ovf = 1;
+                wave_total = nt;
             }
-        }
-        const uint64_t q = kc_wave_sum_checked(acc, &ovf);
-        if (lane == 0) {
-            if (p.per_root) p.per_root[p.rank2id[u]] = q;
-            const uint64_t nt = wave_total + q;
-            if (nt < wave_total) ovf = 1;
-            wave_total = nt;
         }
         wave_sync();
     }
-    if (lane == 0) add_total(p, wave_total, ovf);
+    // per-lane sums of many roots: one exact, carry-checked reduction at the end
+    const uint64_t rest = kc_wave_sum_checked(acc, &ovf);
+    if (lane == 0) {
+        const uint64_t nt = wave_total + rest;
+        if (nt < wave_total) ovf = 1;
+        add_total(p, nt, ovf);
+    }
 }
 
 // ============================================================================
@@ -271,66 +347,116 @@ __host__ __device__ inline uint64_t tri_words(uint64_t d) {
     return tri_rowoff(d, W);
 }
 
-// LDS / scratch layout of one workgroup for out-degree cap D and clique size k
+// Layout of one workgroup's arena (LDS, or a global slice for the scratch tier)
+// for out-degree cap D and clique size K.
 struct WgLayout {
-    size_t nb, seg, colr, delta, bm, stk, bytes;
+    size_t nb, seg, colr, delta, stk, idx, bm, bytes;
     uint32_t W;
 };
-__host__ __device__ inline WgLayout wg_layout(uint32_t D, bool bitmap_inside) {
+__host__ __device__ inline WgLayout wg_layout(uint32_t D, int K) {
     WgLayout L;
     const uint32_t W = (D + 63) / 64;
+    const int levels = K > 3 ? K - 3 : 1;  // wide depth-first stack entries
     L.W = W;
     size_t o = 0;
     L.nb = o;    o += (size_t)D * 4;
     L.seg = o;   o += ((size_t)D + 1) * 4;
     L.colr = o;  o += (size_t)D * 4;
+    L.idx = o;   o += (size_t)WAVES * D;  // local index of each bit, per wave
     o = (o + 7) & ~(size_t)7;
     L.delta = o; o += (size_t)D * 8;
-    L.stk = o;   o += (size_t)WAVES * (KC_KMAX) * W * 8;
-    L.bm = o;
-    if (bitmap_inside) o += tri_words(D) * 8;
+    L.stk = o;   o += (size_t)WAVES * levels * W * 8;
+    L.bm = o;    o += tri_words(D) * 8;
     L.bytes = o;
     return L;
 }
+constexpr size_t WG_STATIC_LDS = sizeof(LocalArea) * WAVES + 128;
 
-template <bool GLOBAL>
-__device__ __forceinline__ uint64_t *bm_row(uint64_t *bm, uint32_t i, uint32_t W) {
-    return bm + tri_rowoff(i, W) - ((i + 1) >> 6);  // index with the absolute word number
+__device__ __forceinline__ const uint64_t *bm_row(const uint64_t *bm, uint32_t i, uint32_t W) {
+    return bm + tri_rowoff(i, W) - ((i + 1) >> 6);  // indexed by absolute word number
+}
+
+// Compact the node set P (words lo..W-1, absolute word index) of at most 64
+// nodes into A: member t = t-th node of P, local row t = its row restricted to P.
+// Returns the number of members.
+__device__ __forceinline__ uint32_t compact_local(const uint64_t *P, uint32_t lo, uint32_t W, const uint64_t *bm,
+                                                  uint32_t Wbm, uint8_t *idx, LocalArea &A) {
+    const uint32_t lane = kc_lane();
+    uint32_t nmem = 0;
+    for (uint32_t l = lo; l < W; ++l) {
+        const uint64_t word = P[l];
+        const bool bit = (word >> lane) & 1ull;
+        const uint64_t bal = __ballot(bit);
+        if (bit) {
+            const uint32_t li = nmem + (uint32_t)__popcll(bal & kc_lanemask_lt());
+            idx[64 * l + lane] = (uint8_t)li;
+            A.members[li] = 64 * l + lane;
+        }
+        nmem += (uint32_t)__popcll(bal);
+    }
+    wave_sync();
+    uint64_t lrow = 0;
+    if (lane < nmem) {
+        const uint32_t v = A.members[lane];
+        const uint64_t *rv = bm_row(bm, v, Wbm);
+        for (uint32_t l = (v + 1) >> 6; l < W; ++l) {
+            uint64_t x = rv[l] & P[l];
+            while (x) {
+                const uint32_t b = (uint32_t)__builtin_ctzll(x);
+                x &= x - 1;
+                lrow |= 1ull << idx[64 * l + b];
+            }
+        }
+    }
+    A.rows[lane] = lrow;
+    wave_sync();
+    return nmem;
 }
 
 template <int K, bool GLOBAL>
 __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
     extern __shared__ __align__(16) unsigned char smem_dyn[];
+    __shared__ LocalArea s_local[WAVES];
     __shared__ uint32_t s_misc[4];
     __shared__ uint64_t s_red[WAVES];
     __shared__ int s_ovf[WAVES];
     unsigned char *arena = GLOBAL ? (unsigned char *)(p.gscratch + (size_t)blockIdx.x * p.slice_words) : smem_dyn;
-    const WgLayout L = wg_layout(p.dcap, true);
+    const WgLayout L = wg_layout(p.dcap, K);
     uint32_t *nb = (uint32_t *)(arena + L.nb);
     uint32_t *seg = (uint32_t *)(arena + L.seg);
     uint32_t *colr = (uint32_t *)(arena + L.colr);
     uint64_t *delta = (uint64_t *)(arena + L.delta);
-    uint64_t *stk_all = (uint64_t *)(arena + L.stk);
     uint64_t *bm = (uint64_t *)(arena + L.bm);
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const uint32_t Wc = L.W;
-    uint64_t *stk = stk_all + (size_t)wave * KC_KMAX * Wc;
+    const int levels = K > 3 ? K - 3 : 1;
+    uint64_t *stk = (uint64_t *)(arena + L.stk) + (size_t)wave * levels * Wc;
+    uint8_t *idxmap = (uint8_t *)(arena + L.idx) + (size_t)wave * p.dcap;
+    LocalArea &A = s_local[wave];
+    const uint32_t chunk = queue_chunk(p.count, gridDim.x);
     uint64_t block_total = 0;
     int ovf = 0;
+    uint32_t cb = 0, cn = 0, ci = 0;
 
     for (;;) {
-        if (tid == 0) s_misc[0] = atomicAdd(p.next, 1u);
-        __syncthreads();
-        const uint32_t qi = s_misc[0];
-        if (qi >= p.count) break;
-        const uint32_t u = p.queue[qi];
+        if (ci >= cn) {
+            if (tid == 0) s_misc[0] = atomicAdd(p.next, chunk);
+            __syncthreads();
+            cb = s_misc[0];
+            __syncthreads();
+            if (cb >= p.count) break;
+            cn = (p.count - cb) < chunk ? (p.count - cb) : chunk;
+            ci = 0;
+        }
+        const uint32_t u = p.queue[cb + ci];
+        ++ci;
         const uint64_t base = p.optr[u];
         uint32_t d = (uint32_t)(p.optr[u + 1] - base);
 
         for (uint32_t t = tid; t < d; t += WG) nb[t] = p.ocol[base + t];
         __syncthreads();
         if (p.colored && p.scheme == KC_COLOR_GLOBAL) {
-            // keep only the nodes of u's colour, preserving order (block scan of flags)
+            // keep only the nodes of u's colour, preserving order
             const uint32_t cu = node_colour(p.seed, p.rank2id[u], p.c);
             for (uint32_t t = tid; t < d; t += WG) seg[t] = node_colour(p.seed, p.rank2id[nb[t]], p.c) == cu ? 1u : 0u;
             __syncthreads();
@@ -352,7 +478,6 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
         }
         __syncthreads();
         if (tid < 64) {
-            // one wave scans the d entries in chunks of 64
             uint32_t carry = 0;
             for (uint32_t c0 = 0; c0 < d; c0 += 64) {
                 const uint32_t t = c0 + lane;
@@ -379,73 +504,98 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                 const uint32_t j = lower_bound_u32(nb, d, y);
                 if (j >= d || nb[j] != y) continue;
                 if (p.colored && p.scheme == KC_COLOR_PER_ROOT && colr[i] != colr[j]) continue;
-                atomicOr((unsigned long long *)(bm_row<GLOBAL>(bm, i, W) + (j >> 6)), 1ull << (j & 63));
+                atomicOr((unsigned long long *)(bm_row(bm, i, W) + (j >> 6)), 1ull << (j & 63));
             }
         }
         if (tid == 0) s_misc[2] = 0;
         __syncthreads();
 
-        // depth-first count, one first-level node per wave at a time
         uint64_t acc = 0;
-        for (;;) {
-            uint32_t i = 0;
-            if (lane == 0) i = atomicAdd(&s_misc[2], 1u);
-            i = __shfl(i, 0, 64);
-            if (i >= d) break;
-            const uint32_t lo0 = (i + 1) >> 6;
-            const uint64_t *ri = bm_row<GLOBAL>(bm, i, W);
-            if (K == 3) {
-                for (uint32_t l = lo0 + lane; l < W; l += 64) acc += (uint64_t)__popcll(ri[l]);
-                continue;
-            }
-            // stack[depth] holds the candidates not yet visited at that depth
-            for (uint32_t l = lo0 + lane; l < W; l += 64) stk[l] = ri[l];
-            uint32_t lo[KC_KMAX];
-            lo[0] = lo0;
-            int depth = 0;
-            wave_sync();
-            while (depth >= 0) {
-                uint64_t *cur = stk + (size_t)depth * Wc;
-                // lowest remaining candidate v at this depth
-                int v = -1;
-                for (uint32_t wb = lo[depth]; wb < W; wb += 64) {
-                    const uint32_t l = wb + lane;
-                    const uint64_t word = l < W ? cur[l] : 0ull;
-                    const uint64_t bal = __ballot(word != 0);
-                    if (bal) {
-                        const uint32_t fl = (uint32_t)__builtin_ctzll(bal);
-                        const uint64_t wsel = __shfl(word, fl, 64);
-                        v = (int)((wb + fl) * 64 + (uint32_t)__builtin_ctzll(wsel));
-                        if (lane == fl) cur[l] = word & (word - 1);
-                        lo[depth] = wb + fl;
-                        break;
+        if (K == 3) {
+            // q_{u,2} = edges of G+(u) = set bits of the whole bitmap
+            for (uint64_t w = tid; w < words; w += WG) acc += (uint64_t)__popcll(bm[w]);
+        } else {
+            // first-level nodes, one per wave at a time
+            for (;;) {
+                uint32_t i = 0;
+                if (lane == 0) i = atomicAdd(&s_misc[2], 1u);
+                i = __shfl(i, 0, 64);
+                if (i >= d) break;
+                const uint32_t lo0 = (i + 1) >> 6;
+                const uint64_t *ri = bm_row(bm, i, W);
+                uint32_t pc = 0;
+                for (uint32_t l = lo0 + lane; l < W; l += 64) pc += (uint32_t)__popcll(ri[l]);
+                pc = kc_wave_sum_u32(pc);
+                if ((int)pc < K - 2) continue;
+                if (K == 4) {
+                    // edges inside row_i: lanes take its members v, sum |row_i n row_v|
+                    for (uint32_t wb = lo0; wb < W; ++wb) {
+                        const uint64_t word = ri[wb];
+                        if ((word >> lane) & 1ull) {
+                            const uint32_t v = 64 * wb + lane;
+                            const uint64_t *rv = bm_row(bm, v, W);
+                            for (uint32_t l = (v + 1) >> 6; l < W; ++l) acc += (uint64_t)__popcll(rv[l] & ri[l]);
+                        }
                     }
-                }
-                wave_sync();
-                if (v < 0) {
-                    --depth;
                     continue;
                 }
-                const int rem = (K - 2) - depth - 1;  // nodes still to choose after v
-                const uint32_t clo = ((uint32_t)v + 1) >> 6;
-                const uint64_t *rv = bm_row<GLOBAL>(bm, (uint32_t)v, W);
-                if (rem == 1) {
-                    for (uint32_t l = clo + lane; l < W; l += 64) acc += (uint64_t)__popcll(cur[l] & rv[l]);
-                } else {
+                if (pc <= 64) {
+                    const uint32_t sN = compact_local(ri, lo0, W, bm, W, idxmap, A);
+                    local_count(A, sN, K - 2, acc);
+                    continue;
+                }
+                // wide depth-first search; stk[depth] = candidates not yet visited
+                for (uint32_t l = lo0 + lane; l < W; l += 64) stk[l] = ri[l];
+                uint32_t lo[KC_KMAX];
+                lo[0] = lo0;
+                int depth = 0;
+                wave_sync();
+                while (depth >= 0) {
+                    uint64_t *cur = stk + (size_t)depth * Wc;
+                    int v = -1;
+                    for (uint32_t wb = lo[depth]; wb < W; wb += 64) {
+                        const uint32_t l = wb + lane;
+                        const uint64_t word = l < W ? cur[l] : 0ull;
+                        const uint64_t bal = __ballot(word != 0);
+                        if (bal) {
+                            const uint32_t fl = (uint32_t)__builtin_ctzll(bal);
+                            const uint64_t wsel = __shfl(word, fl, 64);
+                            v = (int)((wb + fl) * 64 + (uint32_t)__builtin_ctzll(wsel));
+                            if (lane == fl) cur[l] = word & (word - 1);
+                            lo[depth] = wb + fl;
+                            break;
+                        }
+                    }
+                    wave_sync();
+                    if (v < 0) {
+                        --depth;
+                        continue;
+                    }
+                    const int rem = (K - 2) - depth - 1;  // nodes still to choose after v
+                    const uint32_t clo = ((uint32_t)v + 1) >> 6;
+                    const uint64_t *rv = bm_row(bm, (uint32_t)v, W);
+                    if (rem == 1) {
+                        for (uint32_t l = clo + lane; l < W; l += 64) acc += (uint64_t)__popcll(cur[l] & rv[l]);
+                        continue;
+                    }
                     uint64_t *nxt = cur + Wc;
-                    uint32_t pc = 0;
+                    uint32_t cpc = 0;
                     for (uint32_t l = clo + lane; l < W; l += 64) {
                         const uint64_t x = cur[l] & rv[l];
                         nxt[l] = x;
-                        pc += (uint32_t)__popcll(x);
+                        cpc += (uint32_t)__popcll(x);
                     }
-                    pc = kc_wave_sum_u32(pc);
-                    if ((int)pc >= rem) {
+                    cpc = kc_wave_sum_u32(cpc);
+                    wave_sync();
+                    if ((int)cpc < rem) continue;
+                    if (cpc <= 64) {
+                        const uint32_t sN = compact_local(nxt, clo, W, bm, W, idxmap, A);
+                        local_count(A, sN, rem, acc);
+                    } else {
                         ++depth;
                         lo[depth] = clo;
                     }
                 }
-                wave_sync();
             }
         }
         // per-root total over the block
@@ -474,47 +624,6 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
 }
 
 // ----------------------------------------------------------------------------
-template <int K>
-void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors, int cus, size_t lds_max,
-                  hipStream_t s, uint64_t *gscratch, size_t slice_words, uint32_t scratch_blocks) {
-    const uint32_t *queue = q.buf.as<uint32_t>();
-    // scratch tier first: the largest roots
-    if (q.count[2]) {
-        CountParams p = base;
-        p.queue = queue + q.offset[2];
-        p.count = q.count[2];
-        p.next = cursors + 2;
-        p.gscratch = gscratch;
-        p.slice_words = slice_words;
-        p.dcap = q.max_d[2];
-        hipLaunchKernelGGL((k_count_wg<K, true>), dim3(scratch_blocks), dim3(WG), 0, s, p);
-    }
-    if (q.count[1]) {
-        CountParams p = base;
-        p.queue = queue + q.offset[1];
-        p.count = q.count[1];
-        p.next = cursors + 1;
-        p.dcap = q.max_d[1] < 65 ? 65 : q.max_d[1];
-        const WgLayout L = wg_layout(p.dcap, true);
-        const uint32_t per_cu = (uint32_t)(lds_max / (L.bytes + 1024));
-        uint32_t blocks = (uint32_t)cus * (per_cu ? per_cu : 1);
-        if (blocks > q.count[1]) blocks = q.count[1];
-        (void)hipFuncSetAttribute((const void *)&k_count_wg<K, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)L.bytes);
-        hipLaunchKernelGGL((k_count_wg<K, false>), dim3(blocks), dim3(WG), L.bytes, s, p);
-    }
-    if (q.count[0]) {
-        CountParams p = base;
-        p.queue = queue + q.offset[0];
-        p.count = q.count[0];
-        p.next = cursors + 0;
-        uint32_t blocks = (q.count[0] + WAVES - 1) / WAVES;
-        const uint32_t cap = (uint32_t)cus * 8;
-        if (blocks > cap) blocks = cap;
-        hipLaunchKernelGGL((k_count_wave<K>), dim3(blocks), dim3(WG), 0, s, p);
-    }
-}
-
 struct DevInfo {
     int cus = 0;
     size_t lds_max = 0;
@@ -537,28 +646,69 @@ DevInfo dev_info(int device) {
     return di;
 }
 
+template <int K>
+void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors, const DevInfo &di, hipStream_t s,
+                  uint64_t *gscratch, size_t slice_words, uint32_t scratch_blocks) {
+    // scratch tier first: the largest roots
+    if (q.count[2]) {
+        CountParams p = base;
+        p.queue = q.ptr[2];
+        p.count = q.count[2];
+        p.next = cursors + 2;
+        p.gscratch = gscratch;
+        p.slice_words = slice_words;
+        p.dcap = q.max_d[2];
+        hipLaunchKernelGGL((k_count_wg<K, true>), dim3(scratch_blocks), dim3(WG), 0, s, p);
+    }
+    if (q.count[1]) {
+        CountParams p = base;
+        p.queue = q.ptr[1];
+        p.count = q.count[1];
+        p.next = cursors + 1;
+        p.dcap = q.max_d[1] < 65 ? 65 : q.max_d[1];
+        const WgLayout L = wg_layout(p.dcap, K);
+        const size_t per_block = L.bytes + WG_STATIC_LDS + 256;
+        uint32_t per_cu = (uint32_t)(160 * 1024 / per_block);
+        if (per_cu < 1) per_cu = 1;
+        if (per_cu > 8) per_cu = 8;
+        uint32_t blocks = (uint32_t)di.cus * per_cu;
+        if (blocks > q.count[1]) blocks = q.count[1];
+        (void)hipFuncSetAttribute((const void *)&k_count_wg<K, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)L.bytes);
+        hipLaunchKernelGGL((k_count_wg<K, false>), dim3(blocks), dim3(WG), L.bytes, s, p);
+    }
+    if (q.count[0]) {
+        CountParams p = base;
+        p.queue = q.ptr[0];
+        p.count = q.count[0];
+        p.next = cursors + 0;
+        uint32_t blocks = (q.count[0] + WAVES - 1) / WAVES;
+        const uint32_t cap = (uint32_t)di.cus * 8;
+        if (blocks > cap) blocks = cap;
+        hipLaunchKernelGGL((k_count_wave<K>), dim3(blocks), dim3(WG), 0, s, p);
+    }
+}
+
 }  // namespace
 
 // Largest out-degree whose workgroup layout (packed bitmap included) fits in LDS.
-uint32_t kc_lds_dcap(int device) {
+uint32_t kc_lds_dcap(int device, int k) {
     const DevInfo di = dev_info(device);
-    const size_t budget = di.lds_max - 2048;  // static shared arrays of the kernel
+    const size_t budget = di.lds_max - WG_STATIC_LDS - 512;
     uint32_t lo = 64, hi = 1 << 16;
     while (lo < hi) {
         const uint32_t mid = (lo + hi + 1) / 2;
-        if (wg_layout(mid, true).bytes <= budget) lo = mid; else hi = mid - 1;
+        if (wg_layout(mid, k).bytes <= budget) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
 
-size_t kc_scratch_slice_words(uint32_t dmax) {
-    return (wg_layout(dmax, true).bytes + 7) / 8;
-}
+size_t kc_scratch_slice_words(uint32_t dmax, int k) { return (wg_layout(dmax, k).bytes + 7) / 8; }
 
 kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *total, int *overflow) {
     hipStream_t s = g->stream;
     const DevInfo di = dev_info(g->device);
-    const uint32_t dcap = kc_lds_dcap(g->device);
+    const uint32_t dcap = kc_lds_dcap(g->device, a.k);
 
     KC_HIP(hipEventRecord(g->ev[0], s));
     kc_queue q;
@@ -591,16 +741,16 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
     size_t slice_words = 0;
     uint32_t scratch_blocks = 0;
     if (q.count[2]) {
-        slice_words = kc_scratch_slice_words(q.max_d[2]);
+        slice_words = kc_scratch_slice_words(q.max_d[2], a.k);
         scratch_blocks = q.count[2] < (uint32_t)di.cus ? q.count[2] : (uint32_t)di.cus;
         // bound the scratch footprint to 8 GiB
         while (scratch_blocks > 1 && slice_words * 8 * scratch_blocks > (8ull << 30)) scratch_blocks /= 2;
         KC_TRY(kc_tmp_alloc(gscr, slice_words * 8 * scratch_blocks, s));
     }
     switch (a.k) {
-#define KC_CASE(KK)                                                                                           \
-    case KK:                                                                                                  \
-        launch_tiers<KK>(p, q, cursors, di.cus, di.lds_max, s, gscr.as<uint64_t>(), slice_words, scratch_blocks); \
+#define KC_CASE(KK)                                                                               \
+    case KK:                                                                                      \
+        launch_tiers<KK>(p, q, cursors, di, s, gscr.as<uint64_t>(), slice_words, scratch_blocks); \
         break;
         KC_CASE(3)
         KC_CASE(4)
@@ -616,7 +766,8 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
     }
     KC_HIP(hipGetLastError());
     KC_HIP(hipEventRecord(g->ev[2], s));
-    KC_HIP(hipMemcpyAsync(g->h_res, g->d_res, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    uint64_t *h_res = kc_pinned_scratch();
+    KC_HIP(hipMemcpyAsync(h_res, g->d_res, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     KC_HIP(hipStreamSynchronize(s));
     float t_sched = 0.f, t_count = 0.f;
     (void)hipEventElapsedTime(&t_sched, g->ev[0], g->ev[1]);
@@ -625,7 +776,7 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
     gm->t_schedule = t_sched;
     gm->t_count = t_count;
     gm->t_total = t_sched + t_count;
-    *total = g->h_res[0];
-    *overflow = g->h_res[1] != 0;
+    *total = h_res[0];
+    *overflow = h_res[1] != 0;
     return KC_OK;
 }

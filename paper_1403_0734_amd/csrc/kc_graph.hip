@@ -135,8 +135,8 @@ kc_status kc_canonicalise(kc_graph *g, const uint32_t *d_src, const uint32_t *d_
     const uint64_t mask = (B >= 64) ? ~0ull : ((1ull << B) - 1ull);
     const uint64_t sentinel = (2 * B >= 64) ? ~0ull : ((1ull << (2 * B)) - 1ull);
 
-    KC_HIP(hipMalloc(&g->rowptr, ((size_t)n + 1) * sizeof(uint64_t)));
-    KC_HIP(hipMalloc(&g->deg, (size_t)n * sizeof(uint32_t)));
+    KC_TRY(kc_dev_alloc((void **)&g->rowptr, ((size_t)n + 1) * sizeof(uint64_t), s));
+    KC_TRY(kc_dev_alloc((void **)&g->deg, (size_t)n * sizeof(uint32_t), s));
 
     kc_tmp keys, tmp, flag, pos, err, total;
     KC_TRY(kc_tmp_alloc(err, sizeof(uint32_t) * 2, s));
@@ -163,13 +163,13 @@ kc_status kc_canonicalise(kc_graph *g, const uint32_t *d_src, const uint32_t *d_
         KC_HIP(hipMemcpyAsync(&M2, total.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         KC_HIP(hipStreamSynchronize(s));
         // the unique keys stay on the handle until the orientation has used them
-        KC_HIP(hipMalloc(&g->ukeys, (size_t)(M2 ? M2 : 1) * sizeof(uint64_t)));
+        KC_TRY(kc_dev_alloc((void **)&g->ukeys, (size_t)(M2 ? M2 : 1) * sizeof(uint64_t), s));
         hipLaunchKernelGGL(k_compact_u64, dim3(grid_for(N)), dim3(T), 0, s, keys.as<uint64_t>(), flag.as<uint32_t>(),
                            pos.as<uint32_t>(), N, g->ukeys);
         KC_HIP(hipGetLastError());
     }
     g->m = M2 / 2;
-    KC_HIP(hipMalloc(&g->col, (size_t)(M2 ? M2 : 1) * sizeof(uint32_t)));
+    KC_TRY(kc_dev_alloc((void **)&g->col, (size_t)(M2 ? M2 : 1) * sizeof(uint32_t), s));
     const uint64_t *uk = g->ukeys;
     KC_TRY(rows_from_sorted(uk, M2, B, n, g->rowptr, s));
     if (M2) {
@@ -190,10 +190,10 @@ kc_status kc_orient_impl(kc_graph *g) {
     const uint64_t mask = (B >= 64) ? ~0ull : ((1ull << B) - 1ull);
     const size_t M2 = 2 * (size_t)g->m;
 
-    KC_HIP(hipMalloc(&g->optr, ((size_t)n + 1) * sizeof(uint64_t)));
-    KC_HIP(hipMalloc(&g->ocol, (size_t)(g->m ? g->m : 1) * sizeof(uint32_t)));
-    KC_HIP(hipMalloc(&g->rank2id, (size_t)n * sizeof(uint32_t)));
-    KC_HIP(hipMalloc(&g->id2rank, (size_t)n * sizeof(uint32_t)));
+    KC_TRY(kc_dev_alloc((void **)&g->optr, ((size_t)n + 1) * sizeof(uint64_t), s));
+    KC_TRY(kc_dev_alloc((void **)&g->ocol, (size_t)(g->m ? g->m : 1) * sizeof(uint32_t), s));
+    KC_TRY(kc_dev_alloc((void **)&g->rank2id, (size_t)n * sizeof(uint32_t), s));
+    KC_TRY(kc_dev_alloc((void **)&g->id2rank, (size_t)n * sizeof(uint32_t), s));
 
     // 1. ranks: stable sort of (d(x) << B | x) on the degree bits (ids already ascending)
     kc_tmp nk, nk_tmp;
@@ -237,7 +237,7 @@ kc_status kc_orient_impl(kc_graph *g) {
     KC_HIP(hipMemcpyAsync(&g->max_outdeg, maxd.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     KC_HIP(hipStreamSynchronize(s));
     if (g->ukeys) {
-        KC_HIP(hipFree(g->ukeys));
+        KC_HIP(hipFreeAsync(g->ukeys, s));
         g->ukeys = nullptr;
     }
     g->oriented = 1;

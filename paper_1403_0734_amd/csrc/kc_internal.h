@@ -40,6 +40,10 @@ struct kc_tmp {
     T *as() const { return static_cast<T *>(p); }
 };
 kc_status kc_tmp_alloc(kc_tmp &t, size_t bytes, hipStream_t s);
+// Stream-ordered allocation owned by a handle (freed with hipFreeAsync).
+kc_status kc_dev_alloc(void **p, size_t bytes, hipStream_t s);
+// A small pinned host buffer owned by the calling thread (512 bytes).
+uint64_t *kc_pinned_scratch();
 
 // ----------------------------------------------------------------------------
 // The handle.
@@ -70,9 +74,16 @@ struct kc_graph {
     float *mlp = nullptr;  // device weights (KC_MLP_PARAMS floats)
     int mlp_loaded = 0;
 
-    // small result area: device + pinned host mirror
-    uint64_t *d_res = nullptr;  // [0] total, [1] overflow flag, [2..] misc
-    uint64_t *h_res = nullptr;
+    // small result area on the device: [0] total, [1] overflow flag, [2..] cursors
+    uint64_t *d_res = nullptr;
+
+    // degree-ordered work queue, built once per graph: roots with out-degree
+    // above 64 first, then the rest down to out-degree 2, each part by
+    // out-degree descending; plus the out-degree histogram on the host
+    int dq_ready = 0;
+    uint32_t *dq = nullptr;
+    uint32_t dq_wide = 0, dq_narrow = 0;
+    uint64_t *dq_hist = nullptr;  // host, max_outdeg + 1 entries
 
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     float t_schedule = 0.f, t_count = 0.f, t_total = 0.f;
@@ -107,10 +118,10 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
 #define KC_MLP_H 32
 #define KC_MLP_PARAMS (KC_MLP_IN * KC_MLP_H + KC_MLP_H + KC_MLP_H * KC_MLP_H + KC_MLP_H + KC_MLP_H + 1)
 struct kc_queue {
-    kc_tmp buf;          // root ranks, tiers concatenated
-    uint32_t count[4];   // roots per tier: wave, workgroup, scratch, (unused)
-    uint32_t offset[4];
-    uint32_t max_d[4];   // largest out-degree in each tier
+    kc_tmp buf;                // storage when the queue is built per call
+    const uint32_t *ptr[3];    // root ranks of each tier (wave, workgroup, scratch), heaviest first
+    uint32_t count[3];         // roots per tier
+    uint32_t max_d[3];         // largest out-degree in each tier
 };
 kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_max, kc_queue &q);
 kc_status kc_features(const kc_graph *g, float *d_feat, hipStream_t s);

@@ -1,8 +1,8 @@
 // Learned scheduler: placeholder until the MLP kernels land.
 #include "kc_internal.h"
 
-kc_status kc_predict_work(const kc_graph *g, float *d_pred, hipStream_t s) {
-    (void)g; (void)d_pred; (void)s;
+kc_status kc_predict_work(const kc_graph *g, int k, float *d_pred, hipStream_t s) {
+    (void)g; (void)k; (void)d_pred; (void)s;
     return kc_fail(KC_ESTATE, "learned scheduler not available");
 }
 

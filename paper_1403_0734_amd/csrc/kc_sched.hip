@@ -5,32 +5,65 @@
 // resources (Section 7).  Here every root u with |Gamma+(u)| >= k-1 (smaller
 // roots hold no (k-1)-clique: the Reduce-1 filter of Algorithm 1) is placed in
 // a tier and the queue of each tier is ordered heaviest first:
-//   degree policy   tier by out-degree, order by out-degree;
+//   degree policy   tier by out-degree, order by out-degree.  The order does not
+//                   depend on k, so the queue is sorted once per graph; for a
+//                   given k the tiers are prefixes read off an out-degree
+//                   histogram (the narrow part stops at out-degree k-1).
 //   learned policy  order (and promotion of small but dense roots to the
-//                   workgroup tier) by an MLP's predicted log-work.
+//                   workgroup tier) by an MLP's predicted log-work, per call.
+#include <string.h>
+
 #include "kc_internal.h"
 
 namespace {
 
 constexpr int T = 256;
 inline unsigned grid_for(size_t n) { return (unsigned)((n + T - 1) / T); }
+constexpr uint32_t HIST_LDS = 1024;  // out-degrees below this are binned in LDS first
+
+// key = part (wide/narrow) | 24-bit out-degree complement | rank
+__global__ void k_degree_keys(const uint64_t *optr, uint32_t n, uint64_t *keys, uint32_t *flag, uint32_t *hist) {
+    __shared__ uint32_t s_h[HIST_LDS];
+    for (uint32_t i = threadIdx.x; i < HIST_LDS; i += blockDim.x) s_h[i] = 0;
+    __syncthreads();
+    const size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n) {
+        const uint32_t d = (uint32_t)(optr[u + 1] - optr[u]);
+        const uint32_t dc = d < 0xFFFFFFu ? d : 0xFFFFFFu;
+        keys[u] = ((uint64_t)(d <= 64 ? 1u : 0u) << 62) | ((uint64_t)(0xFFFFFFu - dc) << 32) | (uint64_t)u;
+        flag[u] = d >= 2 ? 1u : 0u;
+        if (d < HIST_LDS) atomicAdd(&s_h[d], 1u);
+        else atomicAdd(&hist[d], 1u);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < HIST_LDS; i += blockDim.x)
+        if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
+}
 
 __device__ __forceinline__ void tier_stats(bool active, uint32_t tier, uint32_t d, uint32_t *cnt, uint32_t *mx) {
+    __shared__ uint32_t s_c[3], s_m[3];
+    if (threadIdx.x < 3) s_c[threadIdx.x] = s_m[threadIdx.x] = 0;
+    __syncthreads();
 #pragma unroll
     for (uint32_t t = 0; t < 3; ++t) {
         const bool in = active && tier == t;
         const uint32_t c = (uint32_t)__popcll(__ballot(in));
         const uint32_t m = kc_wave_max_u32(in ? d : 0u);
         if ((threadIdx.x & 63) == 0 && c) {
-            atomicAdd(&cnt[t], c);
-            atomicMax(&mx[t], m);
+            atomicAdd(&s_c[t], c);
+            atomicMax(&s_m[t], m);
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3 && s_c[threadIdx.x]) {
+        atomicAdd(&cnt[threadIdx.x], s_c[threadIdx.x]);
+        atomicMax(&mx[threadIdx.x], s_m[threadIdx.x]);
     }
 }
 
-// key = tier (2 bits) | 24-bit descending priority | rank
-__global__ void k_bin(const uint64_t *optr, uint32_t n, int k, uint32_t dcap, const float *pred, float promote,
-                      uint64_t *keys, uint32_t *flag, uint32_t *cnt, uint32_t *mx) {
+// learned policy: key = tier | descending predicted log-work | rank
+__global__ void k_learned_keys(const uint64_t *optr, uint32_t n, int k, uint32_t dcap, const float *pred,
+                               float promote, uint64_t *keys, uint32_t *flag, uint32_t *cnt, uint32_t *mx) {
     const size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool active = false;
     uint32_t tier = 0, d = 0;
@@ -38,16 +71,11 @@ __global__ void k_bin(const uint64_t *optr, uint32_t n, int k, uint32_t dcap, co
         d = (uint32_t)(optr[u + 1] - optr[u]);
         active = d >= (uint32_t)(k - 1);
         tier = d <= 64 ? 0u : (d <= dcap ? 1u : 2u);
-        uint32_t prio;
-        if (pred) {
-            const float w = pred[u];
-            if (tier == 0 && w >= promote) tier = 1;
-            float s = w * 262144.0f;  // log-work in 2^-18 steps
-            s = s < 0.f ? 0.f : (s > 16777215.f ? 16777215.f : s);
-            prio = 0xFFFFFFu - (uint32_t)s;
-        } else {
-            prio = 0xFFFFFFu - (d < 0xFFFFFFu ? d : 0xFFFFFFu);
-        }
+        const float w = pred[u];
+        if (tier == 0 && w >= promote) tier = 1;
+        float s = w * 262144.0f;  // log-work in 2^-18 steps
+        s = s < 0.f ? 0.f : (s > 16777215.f ? 16777215.f : s);
+        const uint32_t prio = 0xFFFFFFu - (uint32_t)s;
         keys[u] = ((uint64_t)tier << 62) | ((uint64_t)prio << 32) | (uint64_t)u;
         flag[u] = active ? 1u : 0u;
     }
@@ -65,49 +93,123 @@ __global__ void k_queue_from_keys(const uint64_t *keys, uint32_t cnt, uint32_t *
     if (i < cnt) queue[i] = (uint32_t)keys[i];
 }
 
+kc_status build_degree_cache(kc_graph *g) {
+    hipStream_t s = g->stream;
+    const uint32_t n = g->n;
+    const uint32_t hn = g->max_outdeg + 1;
+    kc_tmp keys, keys2, tmp, flag, pos, hist, total;
+    KC_TRY(kc_tmp_alloc(keys, (size_t)n * 8, s));
+    KC_TRY(kc_tmp_alloc(flag, (size_t)n * 4, s));
+    KC_TRY(kc_tmp_alloc(pos, (size_t)n * 4, s));
+    const uint32_t hcap = hn > HIST_LDS ? hn : HIST_LDS;
+    KC_TRY(kc_tmp_alloc(hist, (size_t)hcap * 4, s));
+    KC_TRY(kc_tmp_alloc(total, 8, s));
+    KC_HIP(hipMemsetAsync(hist.p, 0, (size_t)hcap * 4, s));
+    hipLaunchKernelGGL(k_degree_keys, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)g->optr, n,
+                       keys.as<uint64_t>(), flag.as<uint32_t>(), hist.as<uint32_t>());
+    KC_HIP(hipGetLastError());
+    KC_TRY(kc_scan_excl_u32(flag.as<uint32_t>(), pos.as<uint32_t>(), n, total.as<uint32_t>(), s));
+    uint32_t *h = new (std::nothrow) uint32_t[hn + 1];
+    if (!h) return kc_fail(KC_ENOMEM, "host histogram");
+    uint32_t active = 0;
+    KC_HIP(hipMemcpyAsync(h, hist.p, (size_t)hn * 4, hipMemcpyDeviceToHost, s));
+    KC_HIP(hipMemcpyAsync(&active, total.p, 4, hipMemcpyDeviceToHost, s));
+    KC_HIP(hipStreamSynchronize(s));
+    g->dq_hist = new (std::nothrow) uint64_t[hn];
+    if (!g->dq_hist) {
+        delete[] h;
+        return kc_fail(KC_ENOMEM, "host histogram");
+    }
+    uint32_t wide = 0;
+    for (uint32_t d = 0; d < hn; ++d) {
+        g->dq_hist[d] = h[d];
+        if (d > 64) wide += h[d];
+    }
+    delete[] h;
+    g->dq_wide = wide;
+    g->dq_narrow = active - wide;
+    KC_TRY(kc_dev_alloc((void **)&g->dq, (size_t)(active ? active : 1) * 4, s));
+    if (active) {
+        KC_TRY(kc_tmp_alloc(keys2, (size_t)active * 8, s));
+        KC_TRY(kc_tmp_alloc(tmp, (size_t)active * 8, s));
+        hipLaunchKernelGGL(k_compact_keys, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)keys.as<uint64_t>(),
+                           (const uint32_t *)flag.as<uint32_t>(), (const uint32_t *)pos.as<uint32_t>(), n,
+                           keys2.as<uint64_t>());
+        KC_HIP(hipGetLastError());
+        KC_TRY(kc_radix_sort_u64(keys2.as<uint64_t>(), tmp.as<uint64_t>(), active, 32, 64, s));
+        hipLaunchKernelGGL(k_queue_from_keys, dim3(grid_for(active)), dim3(T), 0, s,
+                           (const uint64_t *)keys2.as<uint64_t>(), active, g->dq);
+        KC_HIP(hipGetLastError());
+    }
+    g->dq_ready = 1;
+    return KC_OK;
+}
+
 }  // namespace
 
-kc_status kc_predict_work(const kc_graph *g, float *d_pred, hipStream_t s);
+kc_status kc_predict_work(const kc_graph *g, int k, float *d_pred, hipStream_t s);
 
 kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_max, kc_queue &q) {
     hipStream_t s = g->stream;
     const uint32_t n = g->n;
-    for (int t = 0; t < 4; ++t) q.count[t] = q.offset[t] = q.max_d[t] = 0;
+    for (int t = 0; t < 3; ++t) {
+        q.ptr[t] = nullptr;
+        q.count[t] = q.max_d[t] = 0;
+    }
     if (n == 0 || k < 3) return KC_OK;
 
+    if (policy == KC_SCHED_DEGREE) {
+        kc_graph *gm = const_cast<kc_graph *>(g);
+        if (!g->dq_ready) KC_TRY(build_degree_cache(gm));
+        const uint64_t *hist = g->dq_hist;
+        const uint32_t dmax = g->max_outdeg;
+        uint32_t scratch = 0, narrow = 0;
+        for (uint32_t d = 0; d <= dmax; ++d) {
+            if (!hist[d]) continue;
+            if (d > d_lds_max) {
+                scratch += (uint32_t)hist[d];
+                q.max_d[2] = d;
+            } else if (d > 64) {
+                q.max_d[1] = d;
+            } else if (d >= (uint32_t)(k - 1)) {
+                narrow += (uint32_t)hist[d];
+                q.max_d[0] = d;
+            }
+        }
+        q.ptr[2] = g->dq;
+        q.count[2] = scratch;
+        q.ptr[1] = g->dq + scratch;
+        q.count[1] = g->dq_wide - scratch;
+        q.ptr[0] = g->dq + g->dq_wide;
+        q.count[0] = narrow;
+        return KC_OK;
+    }
+
+    if (!g->mlp_loaded) return kc_fail(KC_ESTATE, "learned schedule requested but no MLP weights are loaded");
     kc_tmp keys, keys2, tmp, flag, pos, stats, pred;
     KC_TRY(kc_tmp_alloc(keys, (size_t)n * 8, s));
     KC_TRY(kc_tmp_alloc(flag, (size_t)n * 4, s));
     KC_TRY(kc_tmp_alloc(pos, (size_t)n * 4, s));
     KC_TRY(kc_tmp_alloc(stats, 8 * 4, s));
+    KC_TRY(kc_tmp_alloc(pred, (size_t)n * 4, s));
     KC_HIP(hipMemsetAsync(stats.p, 0, 8 * 4, s));
-    const float *pr = nullptr;
-    float promote = 3.0e38f;
-    if (policy == KC_SCHED_LEARNED) {
-        if (!g->mlp_loaded) return kc_fail(KC_ESTATE, "learned schedule requested but no MLP weights are loaded");
-        KC_TRY(kc_tmp_alloc(pred, (size_t)n * 4, s));
-        KC_TRY(kc_predict_work(g, pred.as<float>(), s));
-        pr = pred.as<float>();
-        const char *pe = getenv("KC_PROMOTE_LOGWORK");
-        promote = pe ? (float)atof(pe) : 9.0f;
-    }
-    hipLaunchKernelGGL(k_bin, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)g->optr, n, k, d_lds_max, pr,
-                       promote, keys.as<uint64_t>(), flag.as<uint32_t>(), stats.as<uint32_t>(),
-                       stats.as<uint32_t>() + 4);
+    KC_TRY(kc_predict_work(g, k, pred.as<float>(), s));
+    const char *pe = getenv("KC_PROMOTE_LOGWORK");
+    const float promote = pe ? (float)atof(pe) : 9.0f;
+    hipLaunchKernelGGL(k_learned_keys, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)g->optr, n, k, d_lds_max,
+                       (const float *)pred.as<float>(), promote, keys.as<uint64_t>(), flag.as<uint32_t>(),
+                       stats.as<uint32_t>(), stats.as<uint32_t>() + 4);
     KC_HIP(hipGetLastError());
     KC_TRY(kc_scan_excl_u32(flag.as<uint32_t>(), pos.as<uint32_t>(), n, nullptr, s));
-    uint32_t h_stats[8];
-    KC_HIP(hipMemcpyAsync(h_stats, stats.p, sizeof(h_stats), hipMemcpyDeviceToHost, s));
+    uint32_t *h_stats = (uint32_t *)kc_pinned_scratch();
+    KC_HIP(hipMemcpyAsync(h_stats, stats.p, 8 * 4, hipMemcpyDeviceToHost, s));
     KC_HIP(hipStreamSynchronize(s));
     const uint32_t total = h_stats[0] + h_stats[1] + h_stats[2];
+    uint32_t off = 0;
     for (int t = 0; t < 3; ++t) {
         q.count[t] = h_stats[t];
         q.max_d[t] = h_stats[4 + t];
     }
-    q.offset[0] = 0;
-    q.offset[1] = q.count[0];
-    q.offset[2] = q.count[0] + q.count[1];
-    q.offset[3] = total;
     if (total == 0) return KC_OK;
     KC_TRY(kc_tmp_alloc(keys2, (size_t)total * 8, s));
     KC_TRY(kc_tmp_alloc(tmp, (size_t)total * 8, s));
@@ -120,5 +222,9 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
     hipLaunchKernelGGL(k_queue_from_keys, dim3(grid_for(total)), dim3(T), 0, s,
                        (const uint64_t *)keys2.as<uint64_t>(), total, q.buf.as<uint32_t>());
     KC_HIP(hipGetLastError());
+    for (int t = 0; t < 3; ++t) {
+        q.ptr[t] = q.buf.as<uint32_t>() + off;
+        off += q.count[t];
+    }
     return KC_OK;
 }

@@ -1,0 +1,62 @@
+"""Full-size parity on the benchmark workloads, in the launch configuration the
+benchmark times: whole-graph totals against exact counts written by the oracle
+(tests/golden/counts.json, from tests/golden/make_golden.py), and per-root
+counts of sampled roots recomputed live by the oracle one by one."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import graphgen as G
+from paper_1403_0734_amd import kc as K
+
+from gpu_util import announce, device_graph, per_root
+
+pytestmark = pytest.mark.gpu
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "counts.json")))
+
+
+def sample_roots(og, rng, count, heavy):
+    hp, _ = og.high_csr()
+    d = np.diff(hp.astype(np.int64))
+    rnd = rng.choice(og.n, size=count, replace=False)
+    top = np.argsort(-d, kind="stable")[:heavy]
+    return np.unique(np.concatenate([rnd, top])).astype(np.uint32)
+
+
+def check_workload(name, make, sampled_ks, heavy=100, count=3000):
+    gold = GOLD[name]
+    announce(f"{name}: generating")
+    el = make()
+    assert el.digest() == gold["digest"], "generator output changed"
+    h = device_graph(el)
+    n, m, dmax = K.kc_graph_info(h)
+    assert (n, m, dmax) == (gold["n"], gold["m"], gold["max_outdeg"])
+    for k, q in sorted(gold["q"].items()):
+        announce(f"{name}: total k={k}")
+        assert K.kc_count(h, int(k)) == q, (name, k)
+    for rec in gold["colour"]:
+        announce(f"{name}: colour {rec}")
+        e = K.kc_count_colored(h, rec["k"], rec["c"], rec["seed"], rec["scheme"])
+        assert e.raw == rec["raw"], (name, rec)
+    og = O.OracleGraph.from_edgelist(el)
+    rng = np.random.default_rng(7)
+    roots = sample_roots(og, rng, count, heavy)
+    for k in sampled_ks:
+        announce(f"{name}: sampled per-root k={k}")
+        c, _ = per_root(h, n, k)
+        want = og.count_roots(roots, k)
+        assert np.array_equal(c[roots], want), (name, k)
+        if str(k) in gold["q"]:
+            assert int(c.sum(dtype=np.uint64)) == gold["q"][str(k)]
+    K.kc_graph_destroy(h)
+
+
+def test_chung_lu_1m():
+    check_workload("chung_lu_1m", G.workload_chung_lu_1m, [3, 6])
+
+
+def test_planted_4m():
+    check_workload("planted_4m", G.workload_planted, [5, 8], heavy=300)
