@@ -110,19 +110,45 @@ kc_status kc_count_colored(const kc_graph *g, int32_t k, uint32_t c, uint64_t se
  * unpruned depth-first count performs.  3 <= k <= KC_KMAX. */
 kc_status kc_count_per_root(const kc_graph *g, int32_t k, uint64_t *dev_counts, uint64_t *dev_work);
 
-/* Exact q_k of num graphs in one batched, persistent launch sequence; q_out[i] is
- * the count of gs[i].  Every graph must be oriented and bound to the same stream. */
+/* Exact q_k (3 <= k <= KC_KMAX) of num graphs at once; q_out[i] is the count of gs[i].
+ * The graphs are laid side by side on the device as one disjoint union and counted
+ * by the persistent tier kernels from one work queue (ordered by tier, graph and
+ * out-degree); the count launches are captured in a HIP graph that is replayed when
+ * the same graphs (same handles) are counted again at the same k.  Every graph must
+ * be oriented, on the same device and bound to the same stream; num <= 65536. */
 kc_status kc_count_batch(kc_graph *const *gs, uint32_t num, int32_t k, uint64_t *q_out);
 
 /* Scheduling policy for later counts.  For KC_SCHED_LEARNED, weights_path names a
  * weight file written by kc_train_schedule (NULL keeps the weights already loaded). */
 kc_status kc_set_schedule(kc_graph *g, int32_t policy, const char *weights_path);
 
-/* Train the scheduler's MLP (8 features -> 32 -> 32 -> 1, ReLU, fp32) on GPU to
- * predict log(1 + per-root work) at clique size k for the given graphs, for
- * `epochs` full-batch Adam epochs, and write the weights to weights_path. */
+/* Train the scheduler's MLP (8 features -> 32 -> 32 -> 1, ReLU, fp32) on the GPU
+ * to predict log(1 + per-root work) (the work kc_count_per_root reports) of every
+ * root with at least k'-1 high neighbours, for every clique size k' = 4..k, over
+ * the given oriented graphs: `epochs` passes of mini-batch Adam from a seeded
+ * initialisation.  Writes the weights and the feature normalisation to
+ * weights_path; *final_loss (may be NULL) is the last epoch's mean squared error
+ * of the standardised label.  4 <= k <= KC_KMAX. */
 kc_status kc_train_schedule(kc_graph *const *gs, uint32_t num, int32_t k, int32_t epochs, uint64_t seed,
                             const char *weights_path, float *final_loss);
+
+/* Launch tunables (process-wide; counts never depend on them). */
+typedef struct {
+    int32_t wave_dmax;          /* roots with out-degree <= wave_dmax (1..64) go to the one-wave tier */
+    int32_t wg_blocks_per_cu;   /* workgroup-tier blocks per CU, 0 = as many as LDS allows (0..8) */
+    int32_t wave_blocks_per_cu; /* persistent wave-tier blocks of 4 waves per CU (1..16) */
+    int32_t queue_chunk_div;    /* queue chunk = roots / (workers * queue_chunk_div) (1..64) */
+} kc_tuning;
+
+/* Set the tunables (NULL restores the defaults 64, 0, 8, 8); KC_EINVAL outside the ranges. */
+kc_status kc_set_tuning(const kc_tuning *t);
+kc_status kc_get_tuning(kc_tuning *t);
+
+/* Autotuner: times kc_count_batch(gs, num, k) over a grid of tunables, keeps the
+ * fastest and applies it.  Results are cached in the JSON file cache_path (may be
+ * NULL) under a key of the device architecture and the batch's size and k; a
+ * cached entry is applied without timing.  *best (may be NULL) receives it. */
+kc_status kc_autotune(kc_graph *const *gs, uint32_t num, int32_t k, const char *cache_path, kc_tuning *best);
 
 kc_status kc_graph_info(const kc_graph *g, uint32_t *n, uint64_t *m, uint32_t *max_outdeg);
 

@@ -8,8 +8,12 @@
 
 #include "kc_internal.h"
 
+#include <atomic>
+
 namespace {
 thread_local char g_msg[512] = {0};
+std::atomic<uint64_t> g_serial{1};
+kc_tuning_t g_tuning;
 std::mutex g_pool_mu;
 bool g_pool_ready[64] = {false};
 
@@ -59,6 +63,8 @@ kc_status kc_tmp_alloc(kc_tmp &t, size_t bytes, hipStream_t s) {
     return KC_OK;
 }
 
+const kc_tuning_t &kc_tuning_now() { return g_tuning; }
+
 kc_status kc_dev_alloc(void **p, size_t bytes, hipStream_t s) {
     kc_tmp t;
     KC_TRY(kc_tmp_alloc(t, bytes, s));
@@ -95,7 +101,8 @@ const char *kc_status_str(kc_status s) {
 
 void kc_graph_destroy(kc_graph *g) {
     if (!g) return;
-    void *bufs[] = {g->rowptr, g->col, g->deg, g->ukeys, g->optr, g->ocol, g->rank2id, g->id2rank, g->mlp, g->d_res, g->dq};
+    kc_batch_forget(g->serial);
+    void *bufs[] = {g->rowptr, g->col, g->deg, g->ukeys, g->optr, g->ocol, g->rank2id, g->id2rank, g->mlp, g->d_res, g->dq, g->tri};
     for (void *b : bufs)
         if (b) (void)hipFreeAsync(b, g->stream);
     (void)hipStreamSynchronize(g->stream);
@@ -112,6 +119,7 @@ static kc_status create_impl(const uint32_t *src, const uint32_t *dst, uint64_t 
     g->n = n;
     g->m_in = m_in;
     g->idbits = bits_for(n);
+    g->serial = g_serial.fetch_add(1);
     for (auto &e : g->ev) KC_HIP(hipEventCreate(&e));
     KC_TRY(kc_dev_alloc((void **)&g->d_res, 64 * sizeof(uint64_t), g->stream));
     if (!kc_pinned_scratch()) return kc_fail(KC_ENOMEM, "pinned host buffer");
@@ -259,6 +267,32 @@ kc_status kc_get_oriented(const kc_graph *g, uint64_t *optr, uint32_t *ocol, uin
     if (ocol && g->m) KC_HIP(hipMemcpyAsync(ocol, g->ocol, (size_t)g->m * 4, hipMemcpyDeviceToDevice, s));
     if (rank2id) KC_HIP(hipMemcpyAsync(rank2id, g->rank2id, (size_t)g->n * 4, hipMemcpyDeviceToDevice, s));
     KC_HIP(hipStreamSynchronize(s));
+    return KC_OK;
+}
+
+kc_status kc_set_tuning(const kc_tuning *t) {
+    kc_tuning_t v;
+    if (t) {
+        if (t->wave_dmax < 1 || t->wave_dmax > 64) return kc_fail(KC_EINVAL, "wave_dmax must be in [1, 64]");
+        if (t->wg_blocks_per_cu < 0 || t->wg_blocks_per_cu > 8) return kc_fail(KC_EINVAL, "wg_blocks_per_cu in [0, 8]");
+        if (t->wave_blocks_per_cu < 1 || t->wave_blocks_per_cu > 16)
+            return kc_fail(KC_EINVAL, "wave_blocks_per_cu in [1, 16]");
+        if (t->queue_chunk_div < 1 || t->queue_chunk_div > 64) return kc_fail(KC_EINVAL, "queue_chunk_div in [1, 64]");
+        v.wave_dmax = t->wave_dmax;
+        v.wg_blocks_per_cu = t->wg_blocks_per_cu;
+        v.wave_blocks_per_cu = t->wave_blocks_per_cu;
+        v.chunk_div = t->queue_chunk_div;
+    }
+    g_tuning = v;
+    return KC_OK;
+}
+
+kc_status kc_get_tuning(kc_tuning *t) {
+    if (!t) return kc_fail(KC_EINVAL, "NULL argument");
+    t->wave_dmax = g_tuning.wave_dmax;
+    t->wg_blocks_per_cu = g_tuning.wg_blocks_per_cu;
+    t->wave_blocks_per_cu = g_tuning.wave_blocks_per_cu;
+    t->queue_chunk_div = g_tuning.chunk_div;
     return KC_OK;
 }
 

@@ -100,19 +100,26 @@ struct CountParams {
     uint64_t *gscratch;   // scratch tier: per-block slices
     size_t slice_words;   // u64 words per slice
     uint32_t dcap;        // largest d the workgroup layout holds
+    uint32_t chunk_div;   // queue chunk = count / (workers * chunk_div)
+    // batches: graph of every rank and one total per graph (null for one graph)
+    const uint32_t *graph_of;
+    unsigned long long *gtotals;
 };
 
-__device__ __forceinline__ void add_total(const CountParams &p, uint64_t v, int ovf) {
-    if (ovf) atomicOr(p.overflow, 1u);
-    if (v == 0) return;
-    const unsigned long long old = atomicAdd(p.total, (unsigned long long)v);
-    if (old + v < old) atomicOr(p.overflow, 1u);
-}
 
 // Roots per queue fetch: one device-scope atomic serves a chunk of roots.
-__device__ __forceinline__ uint32_t queue_chunk(uint32_t count, uint32_t workers) {
-    const uint32_t c = count / (workers * 8u);
+__device__ __forceinline__ uint32_t queue_chunk(uint32_t count, uint32_t workers, uint32_t div) {
+    const uint32_t c = count / (workers * div);
     return c < 1u ? 1u : (c > 64u ? 64u : c);
+}
+
+// add a (graph's) partial sum to its total, carry-checked
+__device__ __forceinline__ void add_to(const CountParams &p, uint32_t gid, uint64_t v, int ovf) {
+    if (ovf) atomicOr(p.overflow, 1u);
+    if (v == 0) return;
+    unsigned long long *dst = p.gtotals ? p.gtotals + gid : p.total;
+    const unsigned long long old = atomicAdd(dst, (unsigned long long)v);
+    if (old + v < old) atomicOr(p.overflow, 1u);
 }
 
 // ============================================================================
@@ -219,13 +226,15 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
     __shared__ WaveSmem sm_all[WAVES];
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     WaveSmem &sm = sm_all[wave];
-    const uint32_t chunk = queue_chunk(p.count, gridDim.x * WAVES);
+    const uint32_t chunk = queue_chunk(p.count, gridDim.x * WAVES, p.chunk_div);
     const bool single = p.per_root != nullptr || (p.colored && p.scheme == KC_COLOR_GLOBAL);
     uint64_t wave_total = 0, acc = 0;
     int ovf = 0;
     uint32_t cb = 0, cn = 0, ci = 0;  // chunk start, size, next unpacked root
     uint32_t my_u = 0, my_d = 0;      // lane t holds root t of the chunk
+    uint32_t my_g = 0;
     uint64_t my_base = 0;
+    uint32_t cur_g = 0;               // graph whose cliques acc holds (batches)
 
     for (;;) {
         if (ci >= cn) {
@@ -241,10 +250,21 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
                 my_u = p.queue[cb + lane];
                 my_base = p.optr[my_u];
                 my_d = (uint32_t)(p.optr[my_u + 1] - my_base);
+                my_g = p.graph_of ? p.graph_of[my_u] : 0u;
             }
         }
-        // pack roots ci, ci+1, ... while their out-degrees sum to at most 64
-        const bool cand = lane >= ci && lane < cn;
+        // pack roots ci, ci+1, ... of one graph while their out-degrees sum to at most 64
+        const uint32_t pg = __shfl(my_g, ci, 64);
+        if (pg != cur_g) {
+            const uint64_t part = kc_wave_sum_checked(acc, &ovf);
+            acc = 0;
+            if (lane == 0) add_to(p, cur_g, part, ovf);
+            cur_g = pg;
+        }
+        // the pack is a run of the chunk that stays in graph pg
+        const uint64_t other = __ballot(lane >= ci && lane < cn && my_g != pg);
+        const uint32_t run_end = other ? (uint32_t)__builtin_ctzll(other) : cn;
+        const bool cand = lane >= ci && lane < run_end;
         const uint32_t dl = cand ? my_d : 0u;
         const uint32_t incl = kc_wave_incl_u32(dl);
         const uint32_t before = __shfl(incl - dl, ci, 64);  // sum below root ci
@@ -329,7 +349,7 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
     if (lane == 0) {
         const uint64_t nt = wave_total + rest;
         if (nt < wave_total) ovf = 1;
-        add_total(p, nt, ovf);
+        add_to(p, cur_g, nt, ovf);
     }
 }
 
@@ -433,8 +453,9 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
     uint64_t *stk = (uint64_t *)(arena + L.stk) + (size_t)wave * levels * Wc;
     uint8_t *idxmap = (uint8_t *)(arena + L.idx) + (size_t)wave * p.dcap;
     LocalArea &A = s_local[wave];
-    const uint32_t chunk = queue_chunk(p.count, gridDim.x);
+    const uint32_t chunk = queue_chunk(p.count, gridDim.x, p.chunk_div);
     uint64_t block_total = 0;
+    uint32_t cur_g = 0;
     int ovf = 0;
     uint32_t cb = 0, cn = 0, ci = 0;
 
@@ -614,13 +635,19 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                 q = nq;
             }
             if (p.per_root) p.per_root[p.rank2id[u]] = q;
+            const uint32_t gq = p.graph_of ? p.graph_of[u] : 0u;
+            if (gq != cur_g) {
+                add_to(p, cur_g, block_total, ovf);
+                block_total = 0;
+                cur_g = gq;
+            }
             const uint64_t nt = block_total + q;
             if (nt < block_total) ovf = 1;
             block_total = nt;
         }
         __syncthreads();
     }
-    if (tid == 0) add_total(p, block_total, ovf);
+    if (tid == 0) add_to(p, cur_g, block_total, ovf);
 }
 
 // ----------------------------------------------------------------------------
@@ -649,6 +676,7 @@ DevInfo dev_info(int device) {
 template <int K>
 void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors, const DevInfo &di, hipStream_t s,
                   uint64_t *gscratch, size_t slice_words, uint32_t scratch_blocks) {
+    const kc_tuning_t &tu = kc_tuning_now();
     // scratch tier first: the largest roots
     if (q.count[2]) {
         CountParams p = base;
@@ -671,6 +699,7 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
         uint32_t per_cu = (uint32_t)(160 * 1024 / per_block);
         if (per_cu < 1) per_cu = 1;
         if (per_cu > 8) per_cu = 8;
+        if (tu.wg_blocks_per_cu > 0 && (uint32_t)tu.wg_blocks_per_cu < per_cu) per_cu = (uint32_t)tu.wg_blocks_per_cu;
         uint32_t blocks = (uint32_t)di.cus * per_cu;
         if (blocks > q.count[1]) blocks = q.count[1];
         (void)hipFuncSetAttribute((const void *)&k_count_wg<K, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -683,10 +712,15 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
         p.count = q.count[0];
         p.next = cursors + 0;
         uint32_t blocks = (q.count[0] + WAVES - 1) / WAVES;
-        const uint32_t cap = (uint32_t)di.cus * 8;
+        const uint32_t cap = (uint32_t)di.cus * (uint32_t)(tu.wave_blocks_per_cu > 0 ? tu.wave_blocks_per_cu : 8);
         if (blocks > cap) blocks = cap;
         hipLaunchKernelGGL((k_count_wave<K>), dim3(blocks), dim3(WG), 0, s, p);
     }
+}
+
+__global__ void k_fill_u64(uint64_t *p, size_t n, uint64_t v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 }  // namespace
@@ -705,52 +739,52 @@ uint32_t kc_lds_dcap(int device, int k) {
 
 size_t kc_scratch_slice_words(uint32_t dmax, int k) { return (wg_layout(dmax, k).bytes + 7) / 8; }
 
-kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *total, int *overflow) {
-    hipStream_t s = g->stream;
+// Global-memory slices of the scratch tier for this queue.
+kc_status kc_count_scratch(const kc_graph *g, const kc_queue &q, int k, kc_tmp &gscr, size_t &slice_words,
+                           uint32_t &blocks) {
     const DevInfo di = dev_info(g->device);
-    const uint32_t dcap = kc_lds_dcap(g->device, a.k);
+    slice_words = 0;
+    blocks = 0;
+    if (!q.count[2]) return KC_OK;
+    slice_words = kc_scratch_slice_words(q.max_d[2], k);
+    blocks = q.count[2] < (uint32_t)di.cus ? q.count[2] : (uint32_t)di.cus;
+    while (blocks > 1 && slice_words * 8 * blocks > (8ull << 30)) blocks /= 2;  // at most 8 GiB
+    return kc_tmp_alloc(gscr, slice_words * 8 * blocks, g->stream);
+}
 
-    KC_HIP(hipEventRecord(g->ev[0], s));
-    kc_queue q;
-    KC_TRY(kc_build_queue(g, a.k, a.policy, dcap, q));
-    KC_HIP(hipEventRecord(g->ev[1], s));
-
-    // device result area: [0] total, [1] overflow, [2..5] tier cursors
-    KC_HIP(hipMemsetAsync(g->d_res, 0, 8 * sizeof(uint64_t), s));
+// The counting kernels of one queue, enqueued on s with no allocation, no
+// synchronisation and no memset (so the sequence can be captured in a graph).
+// res: [0] total, [1] overflow flag, [2..4] queue cursors; gtotals/graph_of for batches.
+kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_args &a, uint64_t *res,
+                          unsigned long long *gtotals, uint32_t ngraphs, const uint32_t *graph_of, uint64_t *gscratch,
+                          size_t slice_words, uint32_t scratch_blocks, hipStream_t s) {
+    const DevInfo di = dev_info(g->device);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, res, (size_t)8, 0ull);
+    if (gtotals)
+        hipLaunchKernelGGL(k_fill_u64, dim3((ngraphs + 255) / 256), dim3(256), 0, s, (uint64_t *)gtotals,
+                           (size_t)ngraphs, 0ull);
     const char *bias = getenv("KC_TEST_TOTAL_BIAS");  // test hook: forces the overflow path
-    if (bias) {
-        const unsigned long long b = strtoull(bias, nullptr, 0);
-        KC_HIP(hipMemcpyAsync(g->d_res, &b, sizeof(b), hipMemcpyHostToDevice, s));
-    }
+    if (bias && !gtotals)
+        hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, res, (size_t)1, (uint64_t)strtoull(bias, nullptr, 0));
     CountParams p{};
     p.optr = g->optr;
     p.ocol = g->ocol;
     p.rank2id = g->rank2id;
     p.per_root = a.per_root;
-    p.total = (unsigned long long *)g->d_res;
-    p.overflow = (uint32_t *)(g->d_res + 1);
+    p.total = (unsigned long long *)res;
+    p.overflow = (uint32_t *)(res + 1);
     p.colored = a.colored;
     p.scheme = a.scheme;
     p.c = a.c;
     p.seed = a.seed;
-    uint32_t *cursors = (uint32_t *)(g->d_res + 2);
-
-    if (a.per_root) KC_HIP(hipMemsetAsync(a.per_root, 0, (size_t)g->n * sizeof(uint64_t), s));
-
-    kc_tmp gscr;
-    size_t slice_words = 0;
-    uint32_t scratch_blocks = 0;
-    if (q.count[2]) {
-        slice_words = kc_scratch_slice_words(q.max_d[2], a.k);
-        scratch_blocks = q.count[2] < (uint32_t)di.cus ? q.count[2] : (uint32_t)di.cus;
-        // bound the scratch footprint to 8 GiB
-        while (scratch_blocks > 1 && slice_words * 8 * scratch_blocks > (8ull << 30)) scratch_blocks /= 2;
-        KC_TRY(kc_tmp_alloc(gscr, slice_words * 8 * scratch_blocks, s));
-    }
+    p.chunk_div = (uint32_t)(kc_tuning_now().chunk_div > 0 ? kc_tuning_now().chunk_div : 8);
+    p.graph_of = graph_of;
+    p.gtotals = gtotals;
+    uint32_t *cursors = (uint32_t *)(res + 2);
     switch (a.k) {
-#define KC_CASE(KK)                                                                               \
-    case KK:                                                                                      \
-        launch_tiers<KK>(p, q, cursors, di, s, gscr.as<uint64_t>(), slice_words, scratch_blocks); \
+#define KC_CASE(KK)                                                                             \
+    case KK:                                                                                    \
+        launch_tiers<KK>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks);          \
         break;
         KC_CASE(3)
         KC_CASE(4)
@@ -765,6 +799,24 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
             return kc_fail(KC_EINVAL, "k=%d outside the counting kernels' range", a.k);
     }
     KC_HIP(hipGetLastError());
+    return KC_OK;
+}
+
+kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *total, int *overflow) {
+    hipStream_t s = g->stream;
+    const uint32_t dcap = kc_lds_dcap(g->device, a.k);
+
+    KC_HIP(hipEventRecord(g->ev[0], s));
+    kc_queue q;
+    KC_TRY(kc_build_queue(g, a.k, a.policy, dcap, q));
+    KC_HIP(hipEventRecord(g->ev[1], s));
+    if (a.per_root) KC_HIP(hipMemsetAsync(a.per_root, 0, (size_t)g->n * sizeof(uint64_t), s));
+    kc_tmp gscr;
+    size_t slice_words = 0;
+    uint32_t scratch_blocks = 0;
+    KC_TRY(kc_count_scratch(g, q, a.k, gscr, slice_words, scratch_blocks));
+    KC_TRY(kc_count_launch(g, q, a, g->d_res, nullptr, 0, nullptr, gscr.as<uint64_t>(), slice_words, scratch_blocks,
+                           s));
     KC_HIP(hipEventRecord(g->ev[2], s));
     uint64_t *h_res = kc_pinned_scratch();
     KC_HIP(hipMemcpyAsync(h_res, g->d_res, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));

@@ -71,8 +71,9 @@ struct kc_graph {
 
     // schedule
     int policy = KC_SCHED_DEGREE;
-    float *mlp = nullptr;  // device weights (KC_MLP_PARAMS floats)
+    float *mlp = nullptr;   // device weights (KC_MLP_PARAMS floats + normalisation)
     int mlp_loaded = 0;
+    uint64_t *tri = nullptr;  // per-root edges of G+(u) by original id (scheduler feature), cached
 
     // small result area on the device: [0] total, [1] overflow flag, [2..] cursors
     uint64_t *d_res = nullptr;
@@ -81,10 +82,12 @@ struct kc_graph {
     // above 64 first, then the rest down to out-degree 2, each part by
     // out-degree descending; plus the out-degree histogram on the host
     int dq_ready = 0;
+    int dq_wd = 64;  // wave-tier out-degree limit the queue was split at
     uint32_t *dq = nullptr;
     uint32_t dq_wide = 0, dq_narrow = 0;
     uint64_t *dq_hist = nullptr;  // host, max_outdeg + 1 entries
 
+    uint64_t serial = 0;  // unique per handle (batch plans are keyed by it)
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     float t_schedule = 0.f, t_count = 0.f, t_total = 0.f;
 };
@@ -112,6 +115,25 @@ struct kc_count_args {
     int policy = KC_SCHED_DEGREE;
 };
 kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *total, int *overflow);
+struct kc_queue;
+uint32_t kc_lds_dcap(int device, int k);
+kc_status kc_count_scratch(const kc_graph *g, const kc_queue &q, int k, kc_tmp &gscr, size_t &slice_words,
+                           uint32_t &blocks);
+kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_args &a, uint64_t *res,
+                          unsigned long long *gtotals, uint32_t ngraphs, const uint32_t *graph_of, uint64_t *gscratch,
+                          size_t slice_words, uint32_t scratch_blocks, hipStream_t s);
+
+// Drop a cached batch plan that refers to the handle with this serial.
+void kc_batch_forget(uint64_t serial);
+
+// Launch tunables (process-wide; set by kc_set_tuning or kc_autotune).
+struct kc_tuning_t {
+    int wave_dmax = 64;          // roots with out-degree <= this go to the wave tier
+    int wg_blocks_per_cu = 0;    // 0: as many as LDS allows (at most 8)
+    int wave_blocks_per_cu = 8;  // persistent wave-tier blocks per CU
+    int chunk_div = 8;           // queue chunk = roots / (workers * chunk_div), 1..64
+};
+const kc_tuning_t &kc_tuning_now();
 
 // Scheduler (kc_sched.hip)
 #define KC_MLP_IN 8

@@ -22,7 +22,8 @@ inline unsigned grid_for(size_t n) { return (unsigned)((n + T - 1) / T); }
 constexpr uint32_t HIST_LDS = 1024;  // out-degrees below this are binned in LDS first
 
 // key = part (wide/narrow) | 24-bit out-degree complement | rank
-__global__ void k_degree_keys(const uint64_t *optr, uint32_t n, uint64_t *keys, uint32_t *flag, uint32_t *hist) {
+__global__ void k_degree_keys(const uint64_t *optr, uint32_t n, uint32_t wd, uint64_t *keys, uint32_t *flag,
+                              uint32_t *hist) {
     __shared__ uint32_t s_h[HIST_LDS];
     for (uint32_t i = threadIdx.x; i < HIST_LDS; i += blockDim.x) s_h[i] = 0;
     __syncthreads();
@@ -30,7 +31,7 @@ __global__ void k_degree_keys(const uint64_t *optr, uint32_t n, uint64_t *keys, 
     if (u < n) {
         const uint32_t d = (uint32_t)(optr[u + 1] - optr[u]);
         const uint32_t dc = d < 0xFFFFFFu ? d : 0xFFFFFFu;
-        keys[u] = ((uint64_t)(d <= 64 ? 1u : 0u) << 62) | ((uint64_t)(0xFFFFFFu - dc) << 32) | (uint64_t)u;
+        keys[u] = ((uint64_t)(d <= wd ? 1u : 0u) << 62) | ((uint64_t)(0xFFFFFFu - dc) << 32) | (uint64_t)u;
         flag[u] = d >= 2 ? 1u : 0u;
         if (d < HIST_LDS) atomicAdd(&s_h[d], 1u);
         else atomicAdd(&hist[d], 1u);
@@ -62,7 +63,7 @@ __device__ __forceinline__ void tier_stats(bool active, uint32_t tier, uint32_t 
 }
 
 // learned policy: key = tier | descending predicted log-work | rank
-__global__ void k_learned_keys(const uint64_t *optr, uint32_t n, int k, uint32_t dcap, const float *pred,
+__global__ void k_learned_keys(const uint64_t *optr, uint32_t n, int k, uint32_t wd, uint32_t dcap, const float *pred,
                                float promote, uint64_t *keys, uint32_t *flag, uint32_t *cnt, uint32_t *mx) {
     const size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool active = false;
@@ -70,7 +71,7 @@ __global__ void k_learned_keys(const uint64_t *optr, uint32_t n, int k, uint32_t
     if (u < n) {
         d = (uint32_t)(optr[u + 1] - optr[u]);
         active = d >= (uint32_t)(k - 1);
-        tier = d <= 64 ? 0u : (d <= dcap ? 1u : 2u);
+        tier = d <= wd ? 0u : (d <= dcap ? 1u : 2u);
         const float w = pred[u];
         if (tier == 0 && w >= promote) tier = 1;
         float s = w * 262144.0f;  // log-work in 2^-18 steps
@@ -93,8 +94,15 @@ __global__ void k_queue_from_keys(const uint64_t *keys, uint32_t cnt, uint32_t *
     if (i < cnt) queue[i] = (uint32_t)keys[i];
 }
 
-kc_status build_degree_cache(kc_graph *g) {
+kc_status build_degree_cache(kc_graph *g, uint32_t wd) {
     hipStream_t s = g->stream;
+    if (g->dq) {
+        KC_HIP(hipFreeAsync(g->dq, s));
+        g->dq = nullptr;
+    }
+    delete[] g->dq_hist;
+    g->dq_hist = nullptr;
+    g->dq_ready = 0;
     const uint32_t n = g->n;
     const uint32_t hn = g->max_outdeg + 1;
     kc_tmp keys, keys2, tmp, flag, pos, hist, total;
@@ -105,7 +113,7 @@ kc_status build_degree_cache(kc_graph *g) {
     KC_TRY(kc_tmp_alloc(hist, (size_t)hcap * 4, s));
     KC_TRY(kc_tmp_alloc(total, 8, s));
     KC_HIP(hipMemsetAsync(hist.p, 0, (size_t)hcap * 4, s));
-    hipLaunchKernelGGL(k_degree_keys, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)g->optr, n,
+    hipLaunchKernelGGL(k_degree_keys, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)g->optr, n, wd,
                        keys.as<uint64_t>(), flag.as<uint32_t>(), hist.as<uint32_t>());
     KC_HIP(hipGetLastError());
     KC_TRY(kc_scan_excl_u32(flag.as<uint32_t>(), pos.as<uint32_t>(), n, total.as<uint32_t>(), s));
@@ -123,7 +131,7 @@ kc_status build_degree_cache(kc_graph *g) {
     uint32_t wide = 0;
     for (uint32_t d = 0; d < hn; ++d) {
         g->dq_hist[d] = h[d];
-        if (d > 64) wide += h[d];
+        if (d > wd) wide += h[d];
     }
     delete[] h;
     g->dq_wide = wide;
@@ -141,6 +149,7 @@ kc_status build_degree_cache(kc_graph *g) {
                            (const uint64_t *)keys2.as<uint64_t>(), active, g->dq);
         KC_HIP(hipGetLastError());
     }
+    g->dq_wd = (int)wd;
     g->dq_ready = 1;
     return KC_OK;
 }
@@ -157,10 +166,13 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
         q.count[t] = q.max_d[t] = 0;
     }
     if (n == 0 || k < 3) return KC_OK;
+    int wd = kc_tuning_now().wave_dmax;
+    wd = wd < 1 ? 1 : (wd > 64 ? 64 : wd);
+    if ((uint32_t)wd > d_lds_max) wd = (int)d_lds_max;
 
     if (policy == KC_SCHED_DEGREE) {
         kc_graph *gm = const_cast<kc_graph *>(g);
-        if (!g->dq_ready) KC_TRY(build_degree_cache(gm));
+        if (!g->dq_ready || g->dq_wd != wd) KC_TRY(build_degree_cache(gm, (uint32_t)wd));
         const uint64_t *hist = g->dq_hist;
         const uint32_t dmax = g->max_outdeg;
         uint32_t scratch = 0, narrow = 0;
@@ -169,7 +181,7 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
             if (d > d_lds_max) {
                 scratch += (uint32_t)hist[d];
                 q.max_d[2] = d;
-            } else if (d > 64) {
+            } else if (d > (uint32_t)wd) {
                 q.max_d[1] = d;
             } else if (d >= (uint32_t)(k - 1)) {
                 narrow += (uint32_t)hist[d];
@@ -196,7 +208,8 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
     KC_TRY(kc_predict_work(g, k, pred.as<float>(), s));
     const char *pe = getenv("KC_PROMOTE_LOGWORK");
     const float promote = pe ? (float)atof(pe) : 9.0f;
-    hipLaunchKernelGGL(k_learned_keys, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)g->optr, n, k, d_lds_max,
+    hipLaunchKernelGGL(k_learned_keys, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)g->optr, n, k, (uint32_t)wd,
+                       d_lds_max,
                        (const float *)pred.as<float>(), promote, keys.as<uint64_t>(), flag.as<uint32_t>(),
                        stats.as<uint32_t>(), stats.as<uint32_t>() + 4);
     KC_HIP(hipGetLastError());

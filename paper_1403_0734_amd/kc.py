@@ -23,6 +23,7 @@ EXPORTS = [
     "kc_graph_create", "kc_orient", "kc_count", "kc_count_colored", "kc_count_per_root",
     "kc_count_batch", "kc_set_schedule", "kc_train_schedule", "kc_graph_info", "kc_get_csr",
     "kc_get_oriented", "kc_last_timings", "kc_graph_destroy", "kc_status_str",
+    "kc_set_tuning", "kc_get_tuning", "kc_autotune",
 ]
 
 
@@ -35,6 +36,11 @@ class KcError(RuntimeError):
 class kc_estimate(ctypes.Structure):
     _fields_ = [("raw", ctypes.c_uint64), ("estimate", ctypes.c_double), ("estimate_u64", ctypes.c_uint64),
                 ("estimate_fits_u64", ctypes.c_int32), ("scale_exponent", ctypes.c_int32)]
+
+
+class kc_tuning(ctypes.Structure):
+    _fields_ = [("wave_dmax", ctypes.c_int32), ("wg_blocks_per_cu", ctypes.c_int32),
+                ("wave_blocks_per_cu", ctypes.c_int32), ("queue_chunk_div", ctypes.c_int32)]
 
 
 _lib = None
@@ -65,6 +71,9 @@ def load(path: str = LIB_PATH):
                                   ctypes.POINTER(ctypes.c_float)]),
         "kc_graph_destroy": (None, [P]),
         "kc_status_str": (ctypes.c_char_p, [i32]),
+        "kc_set_tuning": (i32, [ctypes.POINTER(kc_tuning)]),
+        "kc_get_tuning": (i32, [ctypes.POINTER(kc_tuning)]),
+        "kc_autotune": (i32, [P, u32, i32, ctypes.c_char_p, ctypes.POINTER(kc_tuning)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -137,6 +146,28 @@ def kc_train_schedule(gs, k: int, epochs: int, seed: int, weights_path: str) -> 
     check(load().kc_train_schedule(arr, len(gs), k, epochs, seed, weights_path.encode(), ctypes.byref(loss)),
           "kc_train_schedule")
     return loss.value
+
+
+def kc_set_tuning(wave_dmax=64, wg_blocks_per_cu=0, wave_blocks_per_cu=8, queue_chunk_div=8, defaults=False):
+    if defaults:
+        check(load().kc_set_tuning(None), "kc_set_tuning")
+        return
+    t = kc_tuning(wave_dmax, wg_blocks_per_cu, wave_blocks_per_cu, queue_chunk_div)
+    check(load().kc_set_tuning(ctypes.byref(t)), "kc_set_tuning")
+
+
+def kc_get_tuning() -> dict:
+    t = kc_tuning()
+    check(load().kc_get_tuning(ctypes.byref(t)), "kc_get_tuning")
+    return {f: getattr(t, f) for f, _ in kc_tuning._fields_}
+
+
+def kc_autotune(gs, k: int, cache_path: str | None = None) -> dict:
+    arr = (ctypes.c_void_p * len(gs))(*gs)
+    t = kc_tuning()
+    check(load().kc_autotune(arr, len(gs), k, cache_path.encode() if cache_path else None, ctypes.byref(t)),
+          "kc_autotune")
+    return {f: getattr(t, f) for f, _ in kc_tuning._fields_}
 
 
 def kc_graph_info(g: int):
