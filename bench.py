@@ -46,6 +46,14 @@ def main():
     ap.add_argument("--schedule", default="degree", choices=["degree", "learned"])
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1403_0734_amd", "sched_weights.bin"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batch (512 graphs, k=5) and schedule-comparison (planted 4M, k=3..8) sections")
+    ap.add_argument("--batch-graphs", type=int, default=512)
+    ap.add_argument("--sched-ks", default="3,4,5,6,7,8")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE) and exit")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "count_kernels_chung_lu_1m.md"),
+                    help="profile summary holding the count kernels' HBM bytes per launch (rocprofv3 counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -55,6 +63,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        a = torch.empty(args.copy_calibration << 20, dtype=torch.uint8, device="cuda:0")
+        a.fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel()}), flush=True)
+        return
 
     import graphgen as G
     from paper_1403_0734_amd import kc as K
@@ -84,6 +102,7 @@ def main():
                 qs[k] = K.kc_count(h, k)
                 if record is not None:
                     record.setdefault(k, []).append(K.kc_last_timings(h))
+                    record.setdefault(("tiers", k), []).append(K.kc_last_tier_timings(h))
             est = K.kc_count_colored(h, ck, cc, cseed, K.KC_COLOR_PER_ROOT)
             if record is not None:
                 record.setdefault("colour", []).append(K.kc_last_timings(h))
@@ -117,17 +136,46 @@ def main():
         per_k[str(k)] = {"q": qs[k], "ms_schedule": round(t_sched, 4), "ms_count": round(t_count, 4),
                          "kcliques_per_s_count": qs[k] / (t_count * 1e-3) if t_count > 0 else None}
     kdom = max(ks, key=lambda k: per_k[str(k)]["ms_count"])
-    # algorithmic work of counting q_k: one neighbourhood intersection per l-clique of
-    # every G+(u), l = 1..k-2, i.e. sum_{j=2}^{k-1} q_j intersections, each at least
-    # one 64-bit AND and one 64-bit popcount = 4 int32 VALU ops
-    inter = info[1] + sum(qs.get(j, 0) for j in range(3, kdom))
-    missing = [j for j in range(3, kdom) if j not in qs]
-    ms = per_k[str(kdom)]["ms_count"]
-    achieved = 4.0 * inter / (ms * 1e-3) if ms > 0 and not missing else None
-    roofline = {"bound": "alu", "kernel": f"count stage k={kdom} (k_count_wave/k_count_wg)",
-                "achieved": achieved, "peak": INT_PEAK, "unit": "int32 op/s",
-                "frac": (achieved / INT_PEAK) if achieved else None, "traffic": None,
-                "work": f"4 ops x {inter} intersections"}
+    tiers = rec[("tiers", kdom)]
+    t_tier = [sum(t[i] for t in tiers) / len(tiers) for i in range(3)]
+    for k in ks:
+        tk = rec[("tiers", k)]
+        per_k[str(k)]["ms_tiers"] = [round(sum(t[i] for t in tk) / len(tk), 4) for i in range(3)]
+    # Algorithmic work of the dominant tier kernel: the unpruned depth-first count
+    # performs one neighbourhood intersection per l-clique of G+(u), l = 1..k-2
+    # (the per-root work label), each at least one 64-bit AND and one 64-bit
+    # popcount = 4 int32 VALU ops.  The label is summed over the tier's roots.
+    tier_names = ["k_count_wave", "k_count_wg", "k_count_wg (scratch)"]
+    dom = max(range(3), key=lambda i: t_tier[i])
+    h = K.kc_graph_create(src.data_ptr(), dst.data_ptr(), el.m_in, el.n, True, stream)
+    K.kc_orient(h)
+    n = el.n
+    cnt = torch.zeros(n, dtype=torch.int64, device=dev)
+    work = torch.zeros(n, dtype=torch.int64, device=dev)
+    K.kc_count_per_root(h, kdom, cnt.data_ptr(), work.data_ptr())
+    optr = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    r2i = torch.zeros(n, dtype=torch.int32, device=dev)
+    K.kc_get_oriented(h, optr.data_ptr(), None, r2i.data_ptr())
+    K.kc_graph_destroy(h)
+    torch.cuda.synchronize()
+    d_rank = np.diff(optr.cpu().numpy())
+    d_id = np.zeros(n, np.int64)
+    d_id[r2i.cpu().numpy().view(np.uint32)] = d_rank
+    w_id = work.cpu().numpy().astype(np.float64)
+    wd = K.kc_get_tuning()["wave_dmax"]
+    in_tier = [(d_id >= kdom - 1) & (d_id <= wd), d_id > wd, np.zeros(n, bool)]
+    inter = float(w_id[in_tier[dom]].sum())
+    ms = t_tier[dom]
+    achieved = 4.0 * inter / (ms * 1e-3) if ms > 0 else None
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        # the profile summary carries the per-launch bytes as one indented JSON line
+        for line in open(args.traffic):
+            if line.startswith("    {"):
+                traffic = json.loads(line).get(f"{tier_names[dom].split()[0]}<{kdom}>")
+    roofline = {"bound": "alu", "kernel": f"{tier_names[dom]}<{kdom}>", "achieved": achieved, "peak": INT_PEAK,
+                "unit": "int32 op/s", "frac": (achieved / INT_PEAK) if achieved else None, "traffic": traffic,
+                "ms_per_launch": ms, "work": f"4 ops x {inter:.6g} intersections (roots of the tier, k={kdom})"}
 
     out = {
         "metric": METRIC, "value": value, "unit": "k-cliques/s", "n_gpus": 1, "steps": args.steps,
@@ -158,7 +206,101 @@ def main():
                                "sample": f"whole workload: build + exact q_k for k={ks} "
                                          f"({c1 - c0:.1f}s build, {c2 - c1:.1f}s counts); "
                                          f"counts {'equal' if ok else 'DIFFER'} to the GPU's"}
+    if not args.no_extras:
+        out["batch"] = bench_batch(args, K, torch, stream)
+        K.kc_set_tuning(defaults=True)  # the batch's tuning does not carry over
+        out["schedule"] = bench_schedule(args, K, torch, stream)
     print(json.dumps(out), flush=True)
+
+
+def _device_graph(K, torch, el, stream):
+    import numpy as np
+    dev = torch.device("cuda:0")
+    src = torch.from_numpy(el.src.view(np.int32)).to(dev)
+    dst = torch.from_numpy(el.dst.view(np.int32)).to(dev)
+    torch.cuda.synchronize()
+    h = K.kc_graph_create(src.data_ptr(), dst.data_ptr(), el.m_in, el.n, True, stream)
+    K.kc_orient(h)
+    return h
+
+
+def bench_batch(args, K, torch, stream):
+    """s/graph for the batch of Chung-Lu graphs at k=5: one batched, graph-captured
+    count sequence against one count call per graph."""
+    import graphgen as G
+    k = 5
+    log(f"batch: generating {args.batch_graphs} graphs")
+    els = G.workload_batch(args.batch_graphs)
+    # a dedicated stream: launches on it can be captured in a HIP graph
+    bs = torch.cuda.Stream()
+    with torch.cuda.stream(bs):
+        hs = [_device_graph(K, torch, el, bs.cuda_stream) for el in els]
+        log("batch: autotuning")
+        cache = os.path.join(ROOT, "gpurun_out", "kc_tune.tsv") if os.path.isdir(os.path.join(ROOT, "gpurun_out")) \
+            else None
+        tuning = K.kc_autotune(hs, k, cache)
+        t0 = time.perf_counter()
+        per_graph = [K.kc_count(h, k) for h in hs]
+        t1 = time.perf_counter()
+        batched = K.kc_count_batch(hs, k)  # plan, eager run, capture
+        reps = []
+        for _ in range(5):
+            t2 = time.perf_counter()
+            batched = K.kc_count_batch(hs, k)
+            reps.append(time.perf_counter() - t2)
+        for h in hs:
+            K.kc_graph_destroy(h)
+    reps.sort()
+    tb = reps[len(reps) // 2]
+    return {"workload": f"{len(els)} Chung-Lu graphs, exponent 2.3, mean 20, n log-uniform in [1000, 200000]",
+            "k": k, "nodes": sum(el.n for el in els), "edges_in": sum(el.m_in for el in els),
+            "q_total": int(sum(batched)), "counts_equal": batched == per_graph,
+            "s_per_batch": tb, "s_per_graph": tb / len(els),
+            "s_per_batch_per_graph_calls": t1 - t0, "speedup_vs_per_graph_calls": (t1 - t0) / tb,
+            "tuning": tuning}
+
+
+def bench_schedule(args, K, torch, stream):
+    """Learned vs degree-binned schedule on the planted-clique Chung-Lu graph:
+    same kernels and counts, only the queue order and tiers differ."""
+    import tempfile
+    import graphgen as G
+    ks = [int(x) for x in args.sched_ks.split(",")]
+    log("schedule: training the MLP on the ER 2000 and Chung-Lu 1M graphs")
+    train = [_device_graph(K, torch, G.workload_er2000(), stream),
+             _device_graph(K, torch, G.workload_chung_lu_1m(), stream)]
+    wpath = os.path.join(tempfile.mkdtemp(), "sched.bin")
+    t0 = time.perf_counter()
+    loss = K.kc_train_schedule(train, max(ks), 20, 1, wpath)
+    t_train = time.perf_counter() - t0
+    for h in train:
+        K.kc_graph_destroy(h)
+    log("schedule: planted workload")
+    el = G.workload_planted()
+    h = _device_graph(K, torch, el, stream)
+    res = {"workload": el.name, "train_loss": loss, "train_seconds": t_train, "per_k": {}}
+    tot = {"degree": 0.0, "learned": 0.0}
+    for k in ks:
+        row = {}
+        for name, pol in (("degree", K.KC_SCHED_DEGREE), ("learned", K.KC_SCHED_LEARNED)):
+            K.kc_set_schedule(h, pol, wpath if pol == K.KC_SCHED_LEARNED else None)
+            q = K.kc_count(h, k)  # warm-up (builds cached structures)
+            ts = []
+            for _ in range(3):
+                q = K.kc_count(h, k)
+                ts.append(K.kc_last_timings(h)[2])
+            ts.sort()
+            row[name] = {"q": q, "ms": ts[1]}
+            tot[name] += ts[1]
+        row["equal"] = row["degree"]["q"] == row["learned"]["q"]
+        row["speedup"] = row["degree"]["ms"] / row["learned"]["ms"] if row["learned"]["ms"] > 0 else None
+        res["per_k"][str(k)] = row
+        log(f"schedule k={k}: degree {row['degree']['ms']:.2f} ms, learned {row['learned']['ms']:.2f} ms")
+    K.kc_graph_destroy(h)
+    res["ms_total_degree"] = tot["degree"]
+    res["ms_total_learned"] = tot["learned"]
+    res["speedup"] = tot["degree"] / tot["learned"] if tot["learned"] > 0 else None
+    return res
 
 
 if __name__ == "__main__":

@@ -158,8 +158,11 @@ kc_status kc_graph_info(const kc_graph *g, uint32_t *n, uint64_t *m, uint32_t *m
 kc_status kc_get_csr(const kc_graph *g, uint64_t *row_ptr, uint32_t *col, uint32_t *deg);
 kc_status kc_get_oriented(const kc_graph *g, uint64_t *optr, uint32_t *ocol, uint32_t *rank2id);
 
-/* Stage timings of the last call (milliseconds, HIP events on the bound stream). */
+/* Stage timings of the last count on this handle (milliseconds, HIP events on the
+ * bound stream): queue building, the counting kernels, and their sum; and each
+ * tier kernel alone (one-wave, workgroup, scratch; 0 for an empty tier). */
 kc_status kc_last_timings(const kc_graph *g, float *ms_schedule, float *ms_count, float *ms_total);
+kc_status kc_last_tier_timings(const kc_graph *g, float *ms_wave, float *ms_workgroup, float *ms_scratch);
 
 void kc_graph_destroy(kc_graph *g);
 const char *kc_status_str(kc_status s);

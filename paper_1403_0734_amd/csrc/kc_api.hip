@@ -296,6 +296,14 @@ kc_status kc_get_tuning(kc_tuning *t) {
     return KC_OK;
 }
 
+kc_status kc_last_tier_timings(const kc_graph *g, float *ms_wave, float *ms_workgroup, float *ms_scratch) {
+    if (!g) return kc_fail(KC_EINVAL, "graph is NULL");
+    if (ms_wave) *ms_wave = g->t_tier[0];
+    if (ms_workgroup) *ms_workgroup = g->t_tier[1];
+    if (ms_scratch) *ms_scratch = g->t_tier[2];
+    return KC_OK;
+}
+
 kc_status kc_last_timings(const kc_graph *g, float *ms_schedule, float *ms_count, float *ms_total) {
     if (!g) return kc_fail(KC_EINVAL, "graph is NULL");
     if (ms_schedule) *ms_schedule = g->t_schedule;

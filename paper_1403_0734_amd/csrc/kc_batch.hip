@@ -216,6 +216,8 @@ kc_status run_plan(Plan &P, uint64_t *q_out) {
             hipGraph_t gr = nullptr;
             if (ok) ok = hipStreamEndCapture(s, &gr) == hipSuccess && st == KC_OK && gr;
             if (ok) ok = hipGraphInstantiate(&P.exec, gr, nullptr, nullptr, 0) == hipSuccess;
+            if (getenv("KC_DEBUG")) fprintf(stderr, "[kc] batch of %u graphs, k=%d: count launches %s\n", P.num, P.k,
+                                            ok ? "captured in a HIP graph" : "not capturable, replayed eagerly");
             if (ok) {
                 P.graph = gr;
             } else {

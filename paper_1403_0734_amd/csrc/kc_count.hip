@@ -433,6 +433,21 @@ __device__ __forceinline__ uint32_t compact_local(const uint64_t *P, uint32_t lo
     return nmem;
 }
 
+// Edges of G+(u) inside the node set C (words lo..W-1, absolute word index):
+// sum over members v of |C n row_v|, one member per lane, 64 members per round.
+__device__ __forceinline__ void wide_edges(const uint64_t *C, uint32_t lo, uint32_t W, const uint64_t *bm,
+                                           uint64_t &acc) {
+    const uint32_t lane = kc_lane();
+    for (uint32_t wb = lo; wb < W; ++wb) {
+        const uint64_t word = C[wb];
+        if ((word >> lane) & 1ull) {
+            const uint32_t v = 64 * wb + lane;
+            const uint64_t *rv = bm_row(bm, v, W);
+            for (uint32_t l = (v + 1) >> 6; l < W; ++l) acc += (uint64_t)__popcll(rv[l] & C[l]);
+        }
+    }
+}
+
 template <int K, bool GLOBAL>
 __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
     extern __shared__ __align__(16) unsigned char smem_dyn[];
@@ -549,15 +564,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                 pc = kc_wave_sum_u32(pc);
                 if ((int)pc < K - 2) continue;
                 if (K == 4) {
-                    // edges inside row_i: lanes take its members v, sum |row_i n row_v|
-                    for (uint32_t wb = lo0; wb < W; ++wb) {
-                        const uint64_t word = ri[wb];
-                        if ((word >> lane) & 1ull) {
-                            const uint32_t v = 64 * wb + lane;
-                            const uint64_t *rv = bm_row(bm, v, W);
-                            for (uint32_t l = (v + 1) >> 6; l < W; ++l) acc += (uint64_t)__popcll(rv[l] & ri[l]);
-                        }
-                    }
+                    wide_edges(ri, lo0, W, bm, acc);
                     continue;
                 }
                 if (pc <= 64) {
@@ -565,7 +572,10 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                     local_count(A, sN, K - 2, acc);
                     continue;
                 }
-                // wide depth-first search; stk[depth] = candidates not yet visited
+                // Wide depth-first search.  stk[depth] holds the candidates not yet
+                // visited of a node that still needs K-2-depth nodes; a child that
+                // needs 2 more is counted by wide_edges, one of at most 64 nodes as a
+                // compacted local graph, a larger one is pushed.
                 for (uint32_t l = lo0 + lane; l < W; l += 64) stk[l] = ri[l];
                 uint32_t lo[KC_KMAX];
                 lo[0] = lo0;
@@ -573,6 +583,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                 wave_sync();
                 while (depth >= 0) {
                     uint64_t *cur = stk + (size_t)depth * Wc;
+                    const int need = (K - 2) - depth;
                     int v = -1;
                     for (uint32_t wb = lo[depth]; wb < W; wb += 64) {
                         const uint32_t l = wb + lane;
@@ -592,13 +603,9 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                         --depth;
                         continue;
                     }
-                    const int rem = (K - 2) - depth - 1;  // nodes still to choose after v
+                    const int cn = need - 1;  // nodes the child still needs (>= 2)
                     const uint32_t clo = ((uint32_t)v + 1) >> 6;
                     const uint64_t *rv = bm_row(bm, (uint32_t)v, W);
-                    if (rem == 1) {
-                        for (uint32_t l = clo + lane; l < W; l += 64) acc += (uint64_t)__popcll(cur[l] & rv[l]);
-                        continue;
-                    }
                     uint64_t *nxt = cur + Wc;
                     uint32_t cpc = 0;
                     for (uint32_t l = clo + lane; l < W; l += 64) {
@@ -608,10 +615,13 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                     }
                     cpc = kc_wave_sum_u32(cpc);
                     wave_sync();
-                    if ((int)cpc < rem) continue;
-                    if (cpc <= 64) {
+                    if ((int)cpc < cn) continue;
+                    if (cn == 2) {
+                        wide_edges(nxt, clo, W, bm, acc);
+                        wave_sync();
+                    } else if (cpc <= 64) {
                         const uint32_t sN = compact_local(nxt, clo, W, bm, W, idxmap, A);
-                        local_count(A, sN, rem, acc);
+                        local_count(A, sN, cn, acc);
                     } else {
                         ++depth;
                         lo[depth] = clo;
@@ -675,8 +685,9 @@ DevInfo dev_info(int device) {
 
 template <int K>
 void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors, const DevInfo &di, hipStream_t s,
-                  uint64_t *gscratch, size_t slice_words, uint32_t scratch_blocks) {
+                  uint64_t *gscratch, size_t slice_words, uint32_t scratch_blocks, hipEvent_t *ev) {
     const kc_tuning_t &tu = kc_tuning_now();
+    if (ev) (void)hipEventRecord(ev[0], s);
     // scratch tier first: the largest roots
     if (q.count[2]) {
         CountParams p = base;
@@ -688,6 +699,7 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
         p.dcap = q.max_d[2];
         hipLaunchKernelGGL((k_count_wg<K, true>), dim3(scratch_blocks), dim3(WG), 0, s, p);
     }
+    if (ev) (void)hipEventRecord(ev[1], s);
     if (q.count[1]) {
         CountParams p = base;
         p.queue = q.ptr[1];
@@ -706,6 +718,7 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
                                   (int)L.bytes);
         hipLaunchKernelGGL((k_count_wg<K, false>), dim3(blocks), dim3(WG), L.bytes, s, p);
     }
+    if (ev) (void)hipEventRecord(ev[2], s);
     if (q.count[0]) {
         CountParams p = base;
         p.queue = q.ptr[0];
@@ -716,6 +729,7 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
         if (blocks > cap) blocks = cap;
         hipLaunchKernelGGL((k_count_wave<K>), dim3(blocks), dim3(WG), 0, s, p);
     }
+    if (ev) (void)hipEventRecord(ev[3], s);
 }
 
 __global__ void k_fill_u64(uint64_t *p, size_t n, uint64_t v) {
@@ -757,7 +771,7 @@ kc_status kc_count_scratch(const kc_graph *g, const kc_queue &q, int k, kc_tmp &
 // res: [0] total, [1] overflow flag, [2..4] queue cursors; gtotals/graph_of for batches.
 kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_args &a, uint64_t *res,
                           unsigned long long *gtotals, uint32_t ngraphs, const uint32_t *graph_of, uint64_t *gscratch,
-                          size_t slice_words, uint32_t scratch_blocks, hipStream_t s) {
+                          size_t slice_words, uint32_t scratch_blocks, hipStream_t s, hipEvent_t *tier_ev) {
     const DevInfo di = dev_info(g->device);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, res, (size_t)8, 0ull);
     if (gtotals)
@@ -784,7 +798,7 @@ kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_a
     switch (a.k) {
 #define KC_CASE(KK)                                                                             \
     case KK:                                                                                    \
-        launch_tiers<KK>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks);          \
+        launch_tiers<KK>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev); \
         break;
         KC_CASE(3)
         KC_CASE(4)
@@ -815,16 +829,20 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
     size_t slice_words = 0;
     uint32_t scratch_blocks = 0;
     KC_TRY(kc_count_scratch(g, q, a.k, gscr, slice_words, scratch_blocks));
+    hipEvent_t tev[4] = {g->ev[2], g->ev[3], g->ev[4], g->ev[5]};
     KC_TRY(kc_count_launch(g, q, a, g->d_res, nullptr, 0, nullptr, gscr.as<uint64_t>(), slice_words, scratch_blocks,
-                           s));
-    KC_HIP(hipEventRecord(g->ev[2], s));
+                           s, tev));
     uint64_t *h_res = kc_pinned_scratch();
     KC_HIP(hipMemcpyAsync(h_res, g->d_res, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     KC_HIP(hipStreamSynchronize(s));
-    float t_sched = 0.f, t_count = 0.f;
+    float t_sched = 0.f, t_count = 0.f, tt[3] = {0.f, 0.f, 0.f};
     (void)hipEventElapsedTime(&t_sched, g->ev[0], g->ev[1]);
-    (void)hipEventElapsedTime(&t_count, g->ev[1], g->ev[2]);
+    (void)hipEventElapsedTime(&t_count, g->ev[1], g->ev[5]);
+    (void)hipEventElapsedTime(&tt[2], g->ev[2], g->ev[3]);
+    (void)hipEventElapsedTime(&tt[1], g->ev[3], g->ev[4]);
+    (void)hipEventElapsedTime(&tt[0], g->ev[4], g->ev[5]);
     kc_graph *gm = const_cast<kc_graph *>(g);
+    for (int t = 0; t < 3; ++t) gm->t_tier[t] = tt[t];
     gm->t_schedule = t_sched;
     gm->t_count = t_count;
     gm->t_total = t_sched + t_count;

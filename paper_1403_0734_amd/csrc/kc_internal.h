@@ -88,8 +88,9 @@ struct kc_graph {
     uint64_t *dq_hist = nullptr;  // host, max_outdeg + 1 entries
 
     uint64_t serial = 0;  // unique per handle (batch plans are keyed by it)
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     float t_schedule = 0.f, t_count = 0.f, t_total = 0.f;
+    float t_tier[3] = {0.f, 0.f, 0.f};  // wave, workgroup, scratch kernels of the last count
 };
 
 // ----------------------------------------------------------------------------
@@ -119,9 +120,12 @@ struct kc_queue;
 uint32_t kc_lds_dcap(int device, int k);
 kc_status kc_count_scratch(const kc_graph *g, const kc_queue &q, int k, kc_tmp &gscr, size_t &slice_words,
                            uint32_t &blocks);
+// tier_ev (may be null): 4 events recorded before the scratch, workgroup and wave
+// tier launches and after the last one.
 kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_args &a, uint64_t *res,
                           unsigned long long *gtotals, uint32_t ngraphs, const uint32_t *graph_of, uint64_t *gscratch,
-                          size_t slice_words, uint32_t scratch_blocks, hipStream_t s);
+                          size_t slice_words, uint32_t scratch_blocks, hipStream_t s,
+                          hipEvent_t *tier_ev = nullptr);
 
 // Drop a cached batch plan that refers to the handle with this serial.
 void kc_batch_forget(uint64_t serial);

@@ -207,7 +207,7 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
     KC_HIP(hipMemsetAsync(stats.p, 0, 8 * 4, s));
     KC_TRY(kc_predict_work(g, k, pred.as<float>(), s));
     const char *pe = getenv("KC_PROMOTE_LOGWORK");
-    const float promote = pe ? (float)atof(pe) : 9.0f;
+    const float promote = pe ? (float)atof(pe) : 14.0f;  // predicted work above ~1.2e6 intersections
     hipLaunchKernelGGL(k_learned_keys, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)g->optr, n, k, (uint32_t)wd,
                        d_lds_max,
                        (const float *)pred.as<float>(), promote, keys.as<uint64_t>(), flag.as<uint32_t>(),

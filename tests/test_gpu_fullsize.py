@@ -60,3 +60,9 @@ def test_chung_lu_1m():
 
 def test_planted_4m():
     check_workload("planted_4m", G.workload_planted, [5, 8], heavy=300)
+
+
+def test_rmat22():
+    """R-MAT scale 22: exact totals at k = 3, 4 and colour-sampled raw counts against
+    the oracle's stored values; per-root counts at k = 5 for 1000 random roots."""
+    check_workload("rmat22", G.workload_rmat22, [5], heavy=0, count=1000)
