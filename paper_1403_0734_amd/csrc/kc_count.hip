@@ -22,8 +22,9 @@
 //              row per node, counted by the lane state machine below.
 //   workgroup  64 < d <= D_LDS: one workgroup per root, packed upper-triangular
 //              bitmap in LDS.  Waves take first-level nodes v; a candidate set
-//              of at most 64 nodes is compacted into a local graph and counted
-//              like a wave-tier root, larger ones are split one level further.
+//              of at most 64 (128) nodes is compacted into a one-word (two-word)
+//              local graph and counted by the lane state machine, larger ones
+//              are split one level further.
 //   scratch    d > D_LDS: as workgroup, bitmap in a global-memory slice.
 // Every count is an exact uint64; sums are carry-checked.
 #include "kc_internal.h"
@@ -131,14 +132,17 @@ __device__ __forceinline__ void add_to(const CountParams &p, uint32_t gid, uint6
 // do not wait for each other's subtrees.
 // Rows of lanes >= s must be zero.
 // ============================================================================
+// NS = depth-first stack entries: counting ell-cliques uses ell - 3 of them.
+template <int NS>
 struct LocalArea {
     uint64_t rows[64];
     uint32_t epre[64];
     uint32_t members[64];
-    uint64_t stk[KC_KMAX - 4][64];
+    uint64_t stk[NS][64];
 };
 
-__device__ __forceinline__ void local_count(LocalArea &A, uint32_t s, int ell, uint64_t &acc) {
+template <int NS>
+__device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int ell, uint64_t &acc) {
     const uint32_t lane = kc_lane();
     const uint64_t row = A.rows[lane];
     if (ell <= 1) {
@@ -204,6 +208,101 @@ __device__ __forceinline__ void local_count(LocalArea &A, uint32_t s, int ell, u
 }
 
 // ============================================================================
+// Two-word local graphs: at most 128 nodes, row t held in rows[t][0..1].  The
+// same edge-task state machine as local_count, with two-word candidate sets.
+// Rows t >= s must be zero.
+// ============================================================================
+template <int NS>
+struct LocalArea2 {
+    uint64_t rows[128][2];
+    uint32_t epre[128];
+    uint32_t members[128];
+    uint64_t stk[NS][2][64];
+};
+
+__device__ __forceinline__ uint32_t select_bit2(uint64_t w0, uint64_t w1, uint32_t r) {
+    const uint32_t c0 = (uint32_t)__popcll(w0);
+    return r < c0 ? select_bit(w0, r) : 64u + select_bit(w1, r - c0);
+}
+
+template <int NS>
+__device__ __forceinline__ void local_count2(LocalArea2<NS> &A, uint32_t s, int ell, uint64_t &acc) {
+    const uint32_t lane = kc_lane();
+    // this lane's two rows 2*lane and 2*lane+1 (consecutive, so the task prefix stays ordered)
+    const uint32_t ca = (uint32_t)(__popcll(A.rows[2 * lane][0]) + __popcll(A.rows[2 * lane][1]));
+    const uint32_t cb = (uint32_t)(__popcll(A.rows[2 * lane + 1][0]) + __popcll(A.rows[2 * lane + 1][1]));
+    if (ell <= 1) {
+        if (lane == 0) acc += ell == 1 ? s : 1u;
+        return;
+    }
+    if (ell == 2) {
+        acc += ca + cb;
+        return;
+    }
+    const int R = ell - 2;
+    const uint32_t incl = kc_wave_incl_u32(ca + cb);
+    const uint32_t E = __shfl(incl, 63, 64);
+    A.epre[2 * lane] = incl - ca - cb;
+    A.epre[2 * lane + 1] = incl - cb;
+    wave_sync();
+    constexpr uint32_t REFILL = 16;
+    int depth = -1;
+    uint32_t next = 0;
+    for (;;) {
+        const uint64_t idle = __ballot(depth < 0);
+        const uint32_t nidle = (uint32_t)__popcll(idle);
+        if (next < E && (nidle >= REFILL || nidle == 64)) {
+            const uint32_t t = next + (uint32_t)__popcll(idle & kc_lanemask_lt());
+            next += nidle;
+            if (depth < 0 && t < E) {
+                const uint32_t i = seg_find(A.epre, s, t);
+                const uint64_t r0 = A.rows[i][0], r1 = A.rows[i][1];
+                const uint32_t j = select_bit2(r0, r1, t - A.epre[i]);
+                const uint64_t p0 = r0 & A.rows[j][0], p1 = r1 & A.rows[j][1];
+                const int pc = __popcll(p0) + __popcll(p1);
+                if (R == 1) {
+                    acc += (uint64_t)pc;
+                } else if (pc >= R) {
+                    depth = 0;
+                    A.stk[0][0][lane] = p0;
+                    A.stk[0][1][lane] = p1;
+                }
+            }
+        } else if (nidle == 64) {
+            break;
+        }
+        if (depth >= 0) {
+            uint64_t c0 = A.stk[depth][0][lane], c1 = A.stk[depth][1][lane];
+            if ((c0 | c1) == 0) {
+                --depth;
+            } else {
+                uint32_t v;
+                if (c0) {
+                    v = (uint32_t)__builtin_ctzll(c0);
+                    c0 &= c0 - 1;
+                } else {
+                    v = 64u + (uint32_t)__builtin_ctzll(c1);
+                    c1 &= c1 - 1;
+                }
+                A.stk[depth][0][lane] = c0;
+                A.stk[depth][1][lane] = c1;
+                const uint64_t h0 = c0 & A.rows[v][0], h1 = c1 & A.rows[v][1];
+                const int pc = __popcll(h0) + __popcll(h1);
+                const int rem = R - depth - 1;
+                if (rem == 1) {
+                    acc += (uint64_t)pc;
+                } else if (pc >= rem) {
+                    ++depth;
+                    A.stk[depth][0][lane] = h0;
+                    A.stk[depth][1][lane] = h1;
+                }
+            }
+        }
+    }
+    wave_sync();
+}
+
+// ============================================================================
 // Wave tier: d <= 64.  Consecutive roots of the queue whose out-degrees sum to
 // at most 64 share one wave pass: their G+(u) are laid side by side as the
 // diagonal blocks of one 64-node local graph (no edge joins two blocks, so its
@@ -211,8 +310,9 @@ __device__ __forceinline__ void local_count(LocalArea &A, uint32_t s, int ell, u
 // are requested, or with the global colouring (which cuts Gamma+(u) first),
 // every pass holds one root.
 // ============================================================================
+template <int K>
 struct WaveSmem {
-    LocalArea A;
+    LocalArea<(K > 4 ? K - 4 : 1)> A;
     uint32_t nb[64];      // the packed Gamma+ lists
     uint32_t seg[64];     // exclusive prefix of their out-degrees
     uint32_t colr[64];
@@ -223,9 +323,9 @@ struct WaveSmem {
 
 template <int K>
 __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
-    __shared__ WaveSmem sm_all[WAVES];
+    __shared__ WaveSmem<K> sm_all[WAVES];
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    WaveSmem &sm = sm_all[wave];
+    WaveSmem<K> &sm = sm_all[wave];
     const uint32_t chunk = queue_chunk(p.count, gridDim.x * WAVES, p.chunk_div);
     const bool single = p.per_root != nullptr || (p.colored && p.scheme == KC_COLOR_GLOBAL);
     uint64_t wave_total = 0, acc = 0;
@@ -390,7 +490,33 @@ __host__ __device__ inline WgLayout wg_layout(uint32_t D, int K) {
     L.bytes = o;
     return L;
 }
-constexpr size_t WG_STATIC_LDS = sizeof(LocalArea) * WAVES + 128;
+// static LDS of the workgroup kernel: one local-graph area per wave (two-word
+// areas from k = 5 on, where candidate sets are compacted) plus small arrays
+// the workgroup tier counts at most (k-2)-cliques in a local graph: k-5 stack entries
+template <int K>
+struct WgAreas {
+    static constexpr int NS = K > 5 ? K - 5 : 1;
+    using A1 = LocalArea<NS>;
+    using A2 = LocalArea2<NS>;
+};
+__host__ __device__ constexpr size_t wg_local_bytes_k(int K, size_t a1, size_t a2) { return K >= 5 ? a2 : a1; }
+template <int K>
+__host__ __device__ constexpr size_t wg_local_bytes() {
+    return wg_local_bytes_k(K, sizeof(typename WgAreas<K>::A1), sizeof(typename WgAreas<K>::A2));
+}
+__host__ __device__ inline size_t wg_local_bytes(int K) {
+    switch (K) {
+        case 3: return wg_local_bytes<3>();
+        case 4: return wg_local_bytes<4>();
+        case 5: return wg_local_bytes<5>();
+        case 6: return wg_local_bytes<6>();
+        case 7: return wg_local_bytes<7>();
+        case 8: return wg_local_bytes<8>();
+        case 9: return wg_local_bytes<9>();
+        default: return wg_local_bytes<10>();
+    }
+}
+__host__ __device__ inline size_t wg_static_lds(int K) { return wg_local_bytes(K) * WAVES + 128; }
 
 __device__ __forceinline__ const uint64_t *bm_row(const uint64_t *bm, uint32_t i, uint32_t W) {
     return bm + tri_rowoff(i, W) - ((i + 1) >> 6);  // indexed by absolute word number
@@ -399,8 +525,9 @@ __device__ __forceinline__ const uint64_t *bm_row(const uint64_t *bm, uint32_t i
 // Compact the node set P (words lo..W-1, absolute word index) of at most 64
 // nodes into A: member t = t-th node of P, local row t = its row restricted to P.
 // Returns the number of members.
+template <class Area>
 __device__ __forceinline__ uint32_t compact_local(const uint64_t *P, uint32_t lo, uint32_t W, const uint64_t *bm,
-                                                  uint32_t Wbm, uint8_t *idx, LocalArea &A) {
+                                                  uint32_t Wbm, uint8_t *idx, Area &A) {
     const uint32_t lane = kc_lane();
     uint32_t nmem = 0;
     for (uint32_t l = lo; l < W; ++l) {
@@ -433,6 +560,48 @@ __device__ __forceinline__ uint32_t compact_local(const uint64_t *P, uint32_t lo
     return nmem;
 }
 
+// As compact_local, for a node set of at most 128 nodes into a two-word local graph.
+template <class Area>
+__device__ __forceinline__ uint32_t compact_local2(const uint64_t *P, uint32_t lo, uint32_t W, const uint64_t *bm,
+                                                   uint32_t Wbm, uint8_t *idx, Area &A) {
+    const uint32_t lane = kc_lane();
+    uint32_t nmem = 0;
+    for (uint32_t l = lo; l < W; ++l) {
+        const uint64_t word = P[l];
+        const bool bit = (word >> lane) & 1ull;
+        const uint64_t bal = __ballot(bit);
+        if (bit) {
+            const uint32_t li = nmem + (uint32_t)__popcll(bal & kc_lanemask_lt());
+            idx[64 * l + lane] = (uint8_t)li;
+            A.members[li] = 64 * l + lane;
+        }
+        nmem += (uint32_t)__popcll(bal);
+    }
+    wave_sync();
+    for (uint32_t half = 0; half < 2; ++half) {
+        const uint32_t t = lane + 64 * half;
+        uint64_t l0 = 0, l1 = 0;
+        if (t < nmem) {
+            const uint32_t v = A.members[t];
+            const uint64_t *rv = bm_row(bm, v, Wbm);
+            for (uint32_t l = (v + 1) >> 6; l < W; ++l) {
+                uint64_t x = rv[l] & P[l];
+                while (x) {
+                    const uint32_t b = (uint32_t)__builtin_ctzll(x);
+                    x &= x - 1;
+                    const uint32_t li = idx[64 * l + b];
+                    if (li < 64) l0 |= 1ull << li;
+                    else l1 |= 1ull << (li - 64);
+                }
+            }
+        }
+        A.rows[t][0] = l0;
+        A.rows[t][1] = l1;
+    }
+    wave_sync();
+    return nmem;
+}
+
 // Edges of G+(u) inside the node set C (words lo..W-1, absolute word index):
 // sum over members v of |C n row_v|, one member per lane, 64 members per round.
 __device__ __forceinline__ void wide_edges(const uint64_t *C, uint32_t lo, uint32_t W, const uint64_t *bm,
@@ -451,7 +620,7 @@ __device__ __forceinline__ void wide_edges(const uint64_t *C, uint32_t lo, uint3
 template <int K, bool GLOBAL>
 __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
     extern __shared__ __align__(16) unsigned char smem_dyn[];
-    __shared__ LocalArea s_local[WAVES];
+    __shared__ __align__(16) uint64_t s_lraw[WAVES][wg_local_bytes<K>() / 8];
     __shared__ uint32_t s_misc[4];
     __shared__ uint64_t s_red[WAVES];
     __shared__ int s_ovf[WAVES];
@@ -467,7 +636,10 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
     const int levels = K > 3 ? K - 3 : 1;
     uint64_t *stk = (uint64_t *)(arena + L.stk) + (size_t)wave * levels * Wc;
     uint8_t *idxmap = (uint8_t *)(arena + L.idx) + (size_t)wave * p.dcap;
-    LocalArea &A = s_local[wave];
+    using A1T = typename WgAreas<K>::A1;
+    using A2T = typename WgAreas<K>::A2;
+    A1T &A = *reinterpret_cast<A1T *>(&s_lraw[wave][0]);
+    A2T &A2 = *reinterpret_cast<A2T *>(&s_lraw[wave][0]);
     const uint32_t chunk = queue_chunk(p.count, gridDim.x, p.chunk_div);
     uint64_t block_total = 0;
     uint32_t cur_g = 0;
@@ -572,6 +744,11 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                     local_count(A, sN, K - 2, acc);
                     continue;
                 }
+                if (K >= 5 && pc <= 128) {
+                    const uint32_t sN = compact_local2(ri, lo0, W, bm, W, idxmap, A2);
+                    local_count2(A2, sN, K - 2, acc);
+                    continue;
+                }
                 // Wide depth-first search.  stk[depth] holds the candidates not yet
                 // visited of a node that still needs K-2-depth nodes; a child that
                 // needs 2 more is counted by wide_edges, one of at most 64 nodes as a
@@ -622,6 +799,9 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                     } else if (cpc <= 64) {
                         const uint32_t sN = compact_local(nxt, clo, W, bm, W, idxmap, A);
                         local_count(A, sN, cn, acc);
+                    } else if (K >= 5 && cpc <= 128) {
+                        const uint32_t sN = compact_local2(nxt, clo, W, bm, W, idxmap, A2);
+                        local_count2(A2, sN, cn, acc);
                     } else {
                         ++depth;
                         lo[depth] = clo;
@@ -707,7 +887,7 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
         p.next = cursors + 1;
         p.dcap = q.max_d[1] < 65 ? 65 : q.max_d[1];
         const WgLayout L = wg_layout(p.dcap, K);
-        const size_t per_block = L.bytes + WG_STATIC_LDS + 256;
+        const size_t per_block = L.bytes + wg_static_lds(K) + 256;
         uint32_t per_cu = (uint32_t)(160 * 1024 / per_block);
         if (per_cu < 1) per_cu = 1;
         if (per_cu > 8) per_cu = 8;
@@ -742,7 +922,7 @@ __global__ void k_fill_u64(uint64_t *p, size_t n, uint64_t v) {
 // Largest out-degree whose workgroup layout (packed bitmap included) fits in LDS.
 uint32_t kc_lds_dcap(int device, int k) {
     const DevInfo di = dev_info(device);
-    const size_t budget = di.lds_max - WG_STATIC_LDS - 512;
+    const size_t budget = di.lds_max - wg_static_lds(k) - 512;
     uint32_t lo = 64, hi = 1 << 16;
     while (lo < hi) {
         const uint32_t mid = (lo + hi + 1) / 2;
