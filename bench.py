@@ -207,7 +207,8 @@ def main():
                                          f"({c1 - c0:.1f}s build, {c2 - c1:.1f}s counts); "
                                          f"counts {'equal' if ok else 'DIFFER'} to the GPU's"}
     if not args.no_extras:
-        out["batch"] = bench_batch(args, K, torch, stream)
+        if args.batch_graphs > 0:
+            out["batch"] = bench_batch(args, K, torch, stream)
         K.kc_set_tuning(defaults=True)  # the batch's tuning does not carry over
         out["schedule"] = bench_schedule(args, K, torch, stream)
     print(json.dumps(out), flush=True)

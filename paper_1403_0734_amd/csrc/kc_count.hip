@@ -102,6 +102,8 @@ struct CountParams {
     size_t slice_words;   // u64 words per slice
     uint32_t dcap;        // largest d the workgroup layout holds
     uint32_t chunk_div;   // queue chunk = count / (workers * chunk_div)
+    // workgroup tier, split roots: item = rank << 32 | part << 16 | parts (null: queue, one part each)
+    const uint64_t *items;
     // batches: graph of every rank and one total per graph (null for one graph)
     const uint32_t *graph_of;
     unsigned long long *gtotals;
@@ -640,7 +642,8 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
     using A2T = typename WgAreas<K>::A2;
     A1T &A = *reinterpret_cast<A1T *>(&s_lraw[wave][0]);
     A2T &A2 = *reinterpret_cast<A2T *>(&s_lraw[wave][0]);
-    const uint32_t chunk = queue_chunk(p.count, gridDim.x, p.chunk_div);
+    // split items are taken one at a time so that the parts of a root spread over blocks
+    const uint32_t chunk = p.items ? 1u : queue_chunk(p.count, gridDim.x, p.chunk_div);
     uint64_t block_total = 0;
     uint32_t cur_g = 0;
     int ovf = 0;
@@ -656,7 +659,15 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
             cn = (p.count - cb) < chunk ? (p.count - cb) : chunk;
             ci = 0;
         }
-        const uint32_t u = p.queue[cb + ci];
+        uint32_t u, part = 0, parts = 1;
+        if (p.items) {
+            const uint64_t it = p.items[cb + ci];
+            u = (uint32_t)(it >> 32);
+            part = (uint32_t)(it >> 16) & 0xFFFFu;
+            parts = (uint32_t)it & 0xFFFFu;
+        } else {
+            u = p.queue[cb + ci];
+        }
         ++ci;
         const uint64_t base = p.optr[u];
         uint32_t d = (uint32_t)(p.optr[u + 1] - base);
@@ -719,15 +730,18 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
         __syncthreads();
 
         uint64_t acc = 0;
-        if (K == 3) {
+        if (K == 3 && parts == 1) {
             // q_{u,2} = edges of G+(u) = set bits of the whole bitmap
             for (uint64_t w = tid; w < words; w += WG) acc += (uint64_t)__popcll(bm[w]);
         } else {
-            // first-level nodes, one per wave at a time
+            // first-level nodes, one per wave at a time; a root split into `parts`
+            // items (Section 7: heavy G+(u) shared by several reducers) takes the
+            // nodes part, part + parts, part + 2 parts, ... in this item
             for (;;) {
-                uint32_t i = 0;
-                if (lane == 0) i = atomicAdd(&s_misc[2], 1u);
-                i = __shfl(i, 0, 64);
+                uint32_t j = 0;
+                if (lane == 0) j = atomicAdd(&s_misc[2], 1u);
+                j = __shfl(j, 0, 64);
+                const uint32_t i = part + j * parts;
                 if (i >= d) break;
                 const uint32_t lo0 = (i + 1) >> 6;
                 const uint64_t *ri = bm_row(bm, i, W);
@@ -824,7 +838,10 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                 if (nq < q || s_ovf[w]) ovf = 1;
                 q = nq;
             }
-            if (p.per_root) p.per_root[p.rank2id[u]] = q;
+            if (p.per_root) {
+                if (parts == 1) p.per_root[p.rank2id[u]] = q;
+                else atomicAdd((unsigned long long *)&p.per_root[p.rank2id[u]], (unsigned long long)q);
+            }
             const uint32_t gq = p.graph_of ? p.graph_of[u] : 0u;
             if (gq != cur_g) {
                 add_to(p, cur_g, block_total, ovf);
@@ -884,6 +901,8 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
         CountParams p = base;
         p.queue = q.ptr[1];
         p.count = q.count[1];
+        p.items = q.wg_items;
+        if (q.wg_items) p.count = q.wg_item_count;
         p.next = cursors + 1;
         p.dcap = q.max_d[1] < 65 ? 65 : q.max_d[1];
         const WgLayout L = wg_layout(p.dcap, K);
@@ -893,7 +912,8 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
         if (per_cu > 8) per_cu = 8;
         if (tu.wg_blocks_per_cu > 0 && (uint32_t)tu.wg_blocks_per_cu < per_cu) per_cu = (uint32_t)tu.wg_blocks_per_cu;
         uint32_t blocks = (uint32_t)di.cus * per_cu;
-        if (blocks > q.count[1]) blocks = q.count[1];
+        const uint32_t nitems = q.wg_items ? q.wg_item_count : q.count[1];
+        if (blocks > nitems) blocks = nitems;
         (void)hipFuncSetAttribute((const void *)&k_count_wg<K, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)L.bytes);
         hipLaunchKernelGGL((k_count_wg<K, false>), dim3(blocks), dim3(WG), L.bytes, s, p);

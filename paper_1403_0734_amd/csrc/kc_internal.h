@@ -145,6 +145,9 @@ const kc_tuning_t &kc_tuning_now();
 #define KC_MLP_PARAMS (KC_MLP_IN * KC_MLP_H + KC_MLP_H + KC_MLP_H * KC_MLP_H + KC_MLP_H + KC_MLP_H + 1)
 struct kc_queue {
     kc_tmp buf;                // storage when the queue is built per call
+    kc_tmp items_buf;
+    const uint64_t *wg_items = nullptr;  // workgroup tier as split items (rank << 32 | part << 16 | parts)
+    uint32_t wg_item_count = 0;
     const uint32_t *ptr[3];    // root ranks of each tier (wave, workgroup, scratch), heaviest first
     uint32_t count[3];         // roots per tier
     uint32_t max_d[3];         // largest out-degree in each tier

@@ -94,6 +94,36 @@ __global__ void k_queue_from_keys(const uint64_t *keys, uint32_t cnt, uint32_t *
     if (i < cnt) queue[i] = (uint32_t)keys[i];
 }
 
+// Split of the workgroup tier (learned policy): a root whose predicted work w is
+// above `target` is cut into ceil(w / target) items (at most smax); item p takes
+// the first-level nodes p, p + parts, ...
+__global__ void k_work_sum(const uint32_t *q, uint32_t cnt, const float *pred, double *sum) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double w = i < cnt ? expm1((double)pred[q[i]]) : 0.0;
+    for (int off = 32; off >= 1; off >>= 1) w += __shfl_xor(w, off, 64);
+    if ((threadIdx.x & 63) == 0 && w != 0.0) atomicAdd(sum, w);
+}
+
+__global__ void k_split_parts(const uint32_t *q, uint32_t cnt, const float *pred, const double *sum, double per,
+                              uint32_t smax, uint32_t *parts) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    const double target = *sum / per > 1.0 ? *sum / per : 1.0;
+    const double w = expm1((double)pred[q[i]]);
+    double np = ceil(w / target);
+    np = np < 1.0 ? 1.0 : (np > (double)smax ? (double)smax : np);
+    parts[i] = (uint32_t)np;
+}
+
+__global__ void k_split_emit(const uint32_t *q, uint32_t cnt, const uint32_t *parts, const uint32_t *off,
+                             uint64_t *items) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    const uint32_t np = parts[i];
+    for (uint32_t pt = 0; pt < np; ++pt)
+        items[off[i] + pt] = ((uint64_t)q[i] << 32) | ((uint64_t)pt << 16) | (uint64_t)np;
+}
+
 kc_status build_degree_cache(kc_graph *g, uint32_t wd) {
     hipStream_t s = g->stream;
     if (g->dq) {
@@ -238,6 +268,34 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
     for (int t = 0; t < 3; ++t) {
         q.ptr[t] = q.buf.as<uint32_t>() + off;
         off += q.count[t];
+    }
+    // heavy workgroup-tier roots are split over several items (k >= 5)
+    if (k >= 5 && q.count[1]) {
+        const uint32_t c1 = q.count[1];
+        kc_tmp sum, parts, offs, ntot;
+        KC_TRY(kc_tmp_alloc(sum, 8, s));
+        KC_TRY(kc_tmp_alloc(parts, (size_t)c1 * 4, s));
+        KC_TRY(kc_tmp_alloc(offs, (size_t)c1 * 4, s));
+        KC_TRY(kc_tmp_alloc(ntot, 4, s));
+        KC_HIP(hipMemsetAsync(sum.p, 0, 8, s));
+        hipLaunchKernelGGL(k_work_sum, dim3(grid_for(c1)), dim3(T), 0, s, q.ptr[1], c1,
+                           (const float *)pred.as<float>(), sum.as<double>());
+        const char *sp = getenv("KC_SPLIT_ITEMS");  // items the tier's predicted work is cut into
+        const double per = sp ? atof(sp) : 4096.0;
+        hipLaunchKernelGGL(k_split_parts, dim3(grid_for(c1)), dim3(T), 0, s, q.ptr[1], c1,
+                           (const float *)pred.as<float>(), (const double *)sum.as<double>(), per, 64u,
+                           parts.as<uint32_t>());
+        KC_TRY(kc_scan_excl_u32(parts.as<uint32_t>(), offs.as<uint32_t>(), c1, ntot.as<uint32_t>(), s));
+        uint32_t nitems = 0;
+        KC_HIP(hipMemcpyAsync(&nitems, ntot.p, 4, hipMemcpyDeviceToHost, s));
+        KC_HIP(hipStreamSynchronize(s));
+        KC_TRY(kc_tmp_alloc(q.items_buf, (size_t)nitems * 8, s));
+        hipLaunchKernelGGL(k_split_emit, dim3(grid_for(c1)), dim3(T), 0, s, q.ptr[1], c1,
+                           (const uint32_t *)parts.as<uint32_t>(), (const uint32_t *)offs.as<uint32_t>(),
+                           q.items_buf.as<uint64_t>());
+        KC_HIP(hipGetLastError());
+        q.wg_items = q.items_buf.as<uint64_t>();
+        q.wg_item_count = nitems;
     }
     return KC_OK;
 }
