@@ -77,6 +77,50 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *nb, uint32_t
     return lo;
 }
 
+// Open-addressing table (LDS) from a node's rank to its position in Gamma+(u):
+// 16-bit slots hold positions (0xFFFF = empty), verified against nb[]; a slot
+// is claimed by a compare-and-swap on the 32-bit word that contains it.
+constexpr uint32_t HEMPTY = 0xFFFFFFFFu;
+__host__ __device__ inline uint32_t hash_bits(uint32_t D) {
+    uint32_t b = 6;
+    while ((1u << b) < 2 * D) ++b;
+    return b;
+}
+__device__ __forceinline__ uint32_t hash_slot(uint32_t y, uint32_t bits) { return (y * 2654435769u) >> (32 - bits); }
+__device__ __forceinline__ void hash_insert(uint16_t *tab, uint32_t bits, uint32_t y, uint32_t pos) {
+    const uint32_t mask = (1u << bits) - 1u;
+    uint32_t h = hash_slot(y, bits);
+    uint32_t *words = reinterpret_cast<uint32_t *>(tab);
+    for (;;) {
+        uint32_t *w = &words[h >> 1];
+        const uint32_t sh = (h & 1u) * 16u;
+        uint32_t old = *w;
+        bool done = false;
+        while (((old >> sh) & 0xFFFFu) == 0xFFFFu) {
+            const uint32_t upd = (old & ~(0xFFFFu << sh)) | (pos << sh);
+            const uint32_t seen = atomicCAS(w, old, upd);
+            if (seen == old) {
+                done = true;
+                break;
+            }
+            old = seen;
+        }
+        if (done) return;
+        h = (h + 1) & mask;
+    }
+}
+// position of y among nb[0, d), or HEMPTY
+__device__ __forceinline__ uint32_t hash_find(const uint16_t *tab, uint32_t bits, const uint32_t *nb, uint32_t y) {
+    const uint32_t mask = (1u << bits) - 1u;
+    uint32_t h = hash_slot(y, bits);
+    for (;;) {
+        const uint32_t j = tab[h];
+        if (j == 0xFFFFu) return HEMPTY;
+        if (nb[j] == y) return j;
+        h = (h + 1) & mask;
+    }
+}
+
 __device__ __forceinline__ uint32_t root_colour(uint64_t seed, uint32_t uid, uint32_t xid, uint32_t c) {
     return kc_colour(kc_mix64(seed ^ kc_mix64(((uint64_t)uid << 32) | xid)), c);
 }
@@ -469,29 +513,6 @@ __host__ __device__ inline uint64_t tri_words(uint64_t d) {
     return tri_rowoff(d, W);
 }
 
-// Layout of one workgroup's arena (LDS, or a global slice for the scratch tier)
-// for out-degree cap D and clique size K.
-struct WgLayout {
-    size_t nb, seg, colr, delta, stk, idx, bm, bytes;
-    uint32_t W;
-};
-__host__ __device__ inline WgLayout wg_layout(uint32_t D, int K) {
-    WgLayout L;
-    const uint32_t W = (D + 63) / 64;
-    const int levels = K > 3 ? K - 3 : 1;  // wide depth-first stack entries
-    L.W = W;
-    size_t o = 0;
-    L.nb = o;    o += (size_t)D * 4;
-    L.seg = o;   o += ((size_t)D + 1) * 4;
-    L.colr = o;  o += (size_t)D * 4;
-    L.idx = o;   o += (size_t)WAVES * D;  // local index of each bit, per wave
-    o = (o + 7) & ~(size_t)7;
-    L.delta = o; o += (size_t)D * 8;
-    L.stk = o;   o += (size_t)WAVES * levels * W * 8;
-    L.bm = o;    o += tri_words(D) * 8;
-    L.bytes = o;
-    return L;
-}
 // static LDS of the workgroup kernel: one local-graph area per wave (two-word
 // areas from k = 5 on, where candidate sets are compacted) plus small arrays
 // the workgroup tier counts at most (k-2)-cliques in a local graph: k-5 stack entries
@@ -519,6 +540,36 @@ __host__ __device__ inline size_t wg_local_bytes(int K) {
     }
 }
 __host__ __device__ inline size_t wg_static_lds(int K) { return wg_local_bytes(K) * WAVES + 128; }
+
+// Layout of one workgroup's arena (LDS, or a global slice for the scratch tier)
+// for out-degree cap D and clique size K.
+struct WgLayout {
+    size_t nb, seg, colr, delta, stk, idx, htab, bm, bytes;
+    uint32_t W, hbits;
+};
+__host__ __device__ inline WgLayout wg_layout(uint32_t D, int K) {
+    WgLayout L;
+    const uint32_t W = (D + 63) / 64;
+    const int levels = K > 3 ? K - 3 : 1;  // wide depth-first stack entries
+    L.W = W;
+    size_t o = 0;
+    L.nb = o;    o += (size_t)D * 4;
+    L.seg = o;   o += ((size_t)D + 1) * 4;
+    L.colr = o;  o += (size_t)D * 4;
+    L.idx = o;   o += (size_t)WAVES * D;  // local index of each bit, per wave
+    o = (o + 3) & ~(size_t)3;
+    L.hbits = hash_bits(D);
+    // the table lives in the per-wave local-graph areas (idle while staging) when it fits
+    const size_t hbytes = ((size_t)1 << L.hbits) * 2;
+    L.htab = hbytes <= wg_local_bytes(K) * WAVES ? (size_t)-1 : o;
+    if (L.htab != (size_t)-1) o += hbytes;
+    o = (o + 7) & ~(size_t)7;
+    L.delta = o; o += (size_t)D * 8;
+    L.stk = o;   o += (size_t)WAVES * levels * W * 8;
+    L.bm = o;    o += tri_words(D) * 8;
+    L.bytes = o;
+    return L;
+}
 
 __device__ __forceinline__ const uint64_t *bm_row(const uint64_t *bm, uint32_t i, uint32_t W) {
     return bm + tri_rowoff(i, W) - ((i + 1) >> 6);  // indexed by absolute word number
@@ -633,6 +684,9 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
     uint32_t *colr = (uint32_t *)(arena + L.colr);
     uint64_t *delta = (uint64_t *)(arena + L.delta);
     uint64_t *bm = (uint64_t *)(arena + L.bm);
+    uint16_t *htab = L.htab == (size_t)-1 ? reinterpret_cast<uint16_t *>(&s_lraw[0][0])
+                                          : (uint16_t *)(arena + L.htab);
+    const uint32_t hbits = L.hbits, hsize = 1u << L.hbits;
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const uint32_t Wc = L.W;
     const int levels = K > 3 ? K - 3 : 1;
@@ -712,18 +766,46 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
         }
         const uint64_t words = tri_words(d);
         for (uint64_t w = tid; w < words; w += WG) bm[w] = 0;
+        for (uint32_t h = tid; h < hsize / 2; h += WG) reinterpret_cast<uint32_t *>(htab)[h] = HEMPTY;
+        if (tid == 0) s_misc[3] = 0;
+        __syncthreads();
+        for (uint32_t t = tid; t < d; t += WG) hash_insert(htab, hbits, nb[t], t);
         __syncthreads();
         const uint32_t Ttot = seg[d];
         if (d > 0) {
             const uint32_t alast = nb[d - 1];
-            for (uint32_t e = tid; e < Ttot; e += WG) {
-                const uint32_t i = seg_find(seg, d, e);
-                const uint32_t y = p.ocol[delta[i] + e];
-                if (y > alast) continue;
-                const uint32_t j = lower_bound_u32(nb, d, y);
-                if (j >= d || nb[j] != y) continue;
-                if (p.colored && p.scheme == KC_COLOR_PER_ROOT && colr[i] != colr[j]) continue;
-                atomicOr((unsigned long long *)(bm_row(bm, i, W) + (j >> 6)), 1ull << (j & 63));
+            if (Ttot >= 32u * d) {
+                // long out-lists: one wave per list, coalesced reads, stop past alast
+                for (;;) {
+                    uint32_t i = 0;
+                    if (lane == 0) i = atomicAdd(&s_misc[3], 1u);
+                    i = __shfl(i, 0, 64);
+                    if (i >= d) break;
+                    const uint64_t b = delta[i] + seg[i];
+                    const uint32_t len = seg[i + 1] - seg[i];
+                    uint64_t *ri = bm + tri_rowoff(i, W) - ((i + 1) >> 6);
+                    for (uint32_t o = 0; o < len; o += 64) {
+                        const uint32_t t = o + lane;
+                        const uint32_t y = t < len ? p.ocol[b + t] : 0xFFFFFFFFu;
+                        const bool in = y <= alast;
+                        if (!__any(in)) break;  // the list is sorted
+                        if (!in) continue;
+                        const uint32_t j = hash_find(htab, hbits, nb, y);
+                        if (j == HEMPTY) continue;
+                        if (p.colored && p.scheme == KC_COLOR_PER_ROOT && colr[i] != colr[j]) continue;
+                        atomicOr((unsigned long long *)(ri + (j >> 6)), 1ull << (j & 63));
+                    }
+                }
+            } else {
+                for (uint32_t e = tid; e < Ttot; e += WG) {
+                    const uint32_t i = seg_find(seg, d, e);
+                    const uint32_t y = p.ocol[delta[i] + e];
+                    if (y > alast) continue;
+                    const uint32_t j = hash_find(htab, hbits, nb, y);
+                    if (j == HEMPTY) continue;
+                    if (p.colored && p.scheme == KC_COLOR_PER_ROOT && colr[i] != colr[j]) continue;
+                    atomicOr((unsigned long long *)(bm_row(bm, i, W) + (j >> 6)), 1ull << (j & 63));
+                }
             }
         }
         if (tid == 0) s_misc[2] = 0;
