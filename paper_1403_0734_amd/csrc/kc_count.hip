@@ -356,16 +356,46 @@ __device__ __forceinline__ void local_count2(LocalArea2<NS> &A, uint32_t s, int 
 // are requested, or with the global colouring (which cuts Gamma+(u) first),
 // every pass holds one root.
 // ============================================================================
+// Staging state of one wave pass, overlaid on the local-graph area (whose
+// rows it shares; the rest of that area is idle until counting starts).
+struct WaveStage {
+    uint64_t rows[64];
+    uint32_t filt[64];  // 2048-bit membership filter of the packed Gamma+ lists
+    uint32_t qy[128];   // ring of filter survivors: out-list element ...
+    uint8_t qi[128];    // ... and the list (local node) it came from
+    uint8_t flag[64];   // per 64-element window: 1 + list starting at each slot
+};
+static_assert(sizeof(WaveStage) <= sizeof(LocalArea<1>), "staging overlay must fit the local-graph area");
+
 template <int K>
 struct WaveSmem {
-    LocalArea<(K > 4 ? K - 4 : 1)> A;
+    union {
+        LocalArea<(K > 4 ? K - 4 : 1)> A;
+        WaveStage S;
+    };
     uint32_t nb[64];      // the packed Gamma+ lists
-    uint32_t seg[64];     // exclusive prefix of their out-degrees
     uint32_t colr[64];
     uint32_t rstart[64];  // first lane of each packed root
     uint8_t blo[64], bhi[64];  // block [blo, bhi) of each lane
-    uint64_t delta[64];
+    uint64_t delta[64];   // out-list base minus its first flattened element
 };
+
+__device__ __forceinline__ uint32_t filt_hash(uint32_t y) { return (y * 2654435769u) >> 21; }
+
+// Exact test of cnt (<= 64) filter survivors from the ring at qh: set bit j of
+// row i when the element y of a_i's out-list is a_j of i's own block.
+template <int K>
+__device__ __forceinline__ void wave_stage_check(WaveSmem<K> &sm, uint32_t qh, uint32_t cnt, bool percol) {
+    const uint32_t lane = kc_lane();
+    if (lane < cnt) {
+        const uint32_t slot = (qh + lane) & 127u;
+        const uint32_t y = sm.S.qy[slot], i = sm.S.qi[slot];
+        const uint32_t lo = sm.blo[i], hi = sm.bhi[i];
+        const uint32_t j = lo + lower_bound_u32(sm.nb + lo, hi - lo, y);
+        if (j < hi && sm.nb[j] == y && (!percol || sm.colr[i] == sm.colr[j]))
+            atomicOr((unsigned long long *)&sm.A.rows[i], 1ull << j);
+    }
+}
 
 template <int K>
 __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
@@ -444,36 +474,83 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
             a = sm.nb[lane];
         }
         sm.nb[lane] = a;
+        const uint32_t lhi = lane < d ? (single ? d : r0 + rd) : 0u;
         sm.blo[lane] = (uint8_t)(lane < d ? r0 : 0u);
-        sm.bhi[lane] = (uint8_t)(lane < d ? (single ? d : r0 + rd) : 0u);
+        sm.bhi[lane] = (uint8_t)lhi;
         uint32_t len = 0;
         uint64_t ob = 0;
         if (lane < d) {
             ob = p.optr[a];
             len = (uint32_t)(p.optr[a + 1] - ob);
         }
+        // only elements up to the largest rank of the block can match: cut each
+        // sorted out-list there (binary lifting when its last element is beyond)
+        const uint32_t bmax = __shfl(a, (lhi ? lhi - 1u : 0u) & 63u, 64);
+        if (len) {
+            const uint32_t *row = p.ocol + ob;
+            if (row[len - 1] > bmax) {
+                uint32_t b = 0;
+                for (uint32_t st = 1u << (31 - __builtin_clz(len)); st; st >>= 1)
+                    if (b + st <= len && row[b + st - 1] <= bmax) b += st;
+                len = b;
+            }
+        }
         const uint32_t sincl = kc_wave_incl_u32(len);
         const uint32_t excl = sincl - len;
         const uint32_t Ttot = __shfl(sincl, 63, 64);
-        sm.seg[lane] = excl;
         sm.delta[lane] = ob - excl;
         sm.A.rows[lane] = 0;
-        if (p.colored && p.scheme == KC_COLOR_PER_ROOT)
-            sm.colr[lane] = lane < d ? root_colour(p.seed, p.rank2id[u], p.rank2id[a], p.c) : 0u;
+        sm.S.filt[lane] = 0;
+        sm.S.flag[lane] = 0;
+        const bool percol = p.colored && p.scheme == KC_COLOR_PER_ROOT;
+        if (percol) sm.colr[lane] = lane < d ? root_colour(p.seed, p.rank2id[u], p.rank2id[a], p.c) : 0u;
+        wave_sync();
+        if (lane < d) {
+            const uint32_t h = filt_hash(a);
+            atomicOr(&sm.S.filt[h >> 5], 1u << (h & 31u));
+        }
         wave_sync();
 
-        // staging: row i bit j = [a_j in Gamma+(a_i)], j inside i's block
-        if (d > 0) {
-            for (uint32_t e = lane; e < Ttot; e += 64) {
-                const uint32_t i = seg_find(sm.seg, d, e);
-                const uint32_t y = p.ocol[sm.delta[i] + e];
-                const uint32_t lo = sm.blo[i], hi = sm.bhi[i];
-                if (y > sm.nb[hi - 1]) continue;
-                const uint32_t j = lo + lower_bound_u32(sm.nb + lo, hi - lo, y);
-                if (sm.nb[j] != y) continue;
-                if (p.colored && p.scheme == KC_COLOR_PER_ROOT && sm.colr[i] != sm.colr[j]) continue;
-                atomicOr((unsigned long long *)&sm.A.rows[i], 1ull << j);
+        // staging: row i bit j = [a_j in Gamma+(a_i)], j inside i's block.  The
+        // flattened out-lists are read 64 elements per step; the list of each
+        // element is the last one starting at or before it (window start flags
+        // and a ballot); the filter drops most non-members, the rest queue up
+        // for an exact search 64 at a time.
+        uint32_t carry = 0, qh = 0, qt = 0;
+        for (uint32_t w0 = 0; w0 < Ttot; w0 += 64) {
+            if (len && excl >= w0 && excl - w0 < 64u) sm.S.flag[excl - w0] = (uint8_t)(lane + 1u);
+            wave_sync();
+            const uint32_t f = sm.S.flag[lane];
+            const uint64_t le = __ballot(f != 0) & (kc_lanemask_lt() | (1ull << lane));
+            const uint32_t fo = __shfl(f, le ? 63u - (uint32_t)__builtin_clzll(le) : 0u, 64);
+            const uint32_t i = le ? fo - 1u : carry;
+            carry = __shfl(i, 63, 64);
+            if (f) sm.S.flag[lane] = 0;
+            const uint32_t e = w0 + lane;
+            bool keep = false;
+            uint32_t y = 0;
+            if (e < Ttot) {
+                y = p.ocol[sm.delta[i] + e];
+                const uint32_t h = filt_hash(y);
+                keep = (sm.S.filt[h >> 5] >> (h & 31u)) & 1u;
             }
+            const uint64_t kb = __ballot(keep);
+            if (keep) {
+                const uint32_t slot = (qt + (uint32_t)__popcll(kb & kc_lanemask_lt())) & 127u;
+                sm.S.qy[slot] = y;
+                sm.S.qi[slot] = (uint8_t)i;
+            }
+            qt += (uint32_t)__popcll(kb);
+            if (qt - qh >= 64u) {
+                wave_sync();
+                wave_stage_check(sm, qh, 64u, percol);
+                qh += 64u;
+                wave_sync();
+            }
+        }
+        if (qt != qh) {
+            wave_sync();
+            wave_stage_check(sm, qh, qt - qh, percol);
         }
         wave_sync();
         local_count(sm.A, d, K - 1, acc);
