@@ -14,8 +14,6 @@ namespace {
 thread_local char g_msg[512] = {0};
 std::atomic<uint64_t> g_serial{1};
 kc_tuning_t g_tuning;
-std::mutex g_pool_mu;
-bool g_pool_ready[64] = {false};
 
 inline int bits_for(uint32_t n) {
     int b = 1;
@@ -40,27 +38,12 @@ kc_status kc_hip_fail(hipError_t e, const char *what, const char *file, int line
 }
 
 kc_status kc_tmp_alloc(kc_tmp &t, size_t bytes, hipStream_t s) {
-    int dev = 0;
-    KC_HIP(hipGetDevice(&dev));
-    if (dev >= 0 && dev < 64 && !g_pool_ready[dev]) {
-        std::lock_guard<std::mutex> lk(g_pool_mu);
-        if (!g_pool_ready[dev]) {
-            hipMemPool_t pool;
-            if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-                uint64_t thr = ~0ull;
-                (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-            }
-            g_pool_ready[dev] = true;
-        }
-    }
     if (t.p) {
-        (void)hipFreeAsync(t.p, t.s);
+        kc_cache_free(t.p, t.s);
         t.p = nullptr;
     }
     t.s = s;
-    if (bytes == 0) bytes = 8;
-    KC_HIP(hipMallocAsync(&t.p, bytes, s));
-    return KC_OK;
+    return kc_cache_alloc(&t.p, bytes ? bytes : 8, s);
 }
 
 const kc_tuning_t &kc_tuning_now() { return g_tuning; }
@@ -71,6 +54,21 @@ kc_status kc_dev_alloc(void **p, size_t bytes, hipStream_t s) {
     *p = t.p;
     t.p = nullptr;  // ownership moves to the caller
     return KC_OK;
+}
+
+void *kc_pinned_buffer(size_t bytes) {
+    static thread_local void *buf = nullptr;
+    static thread_local size_t cap = 0;
+    if (bytes > cap) {
+        if (buf) (void)hipHostFree(buf);
+        buf = nullptr;
+        cap = 0;
+        size_t c = 4096;
+        while (c < bytes) c <<= 1;
+        if (hipHostMalloc(&buf, c, hipHostMallocDefault) != hipSuccess) return nullptr;
+        cap = c;
+    }
+    return buf;
 }
 
 uint64_t *kc_pinned_scratch() {
@@ -104,8 +102,8 @@ void kc_graph_destroy(kc_graph *g) {
     kc_batch_forget(g->serial);
     void *bufs[] = {g->rowptr, g->col, g->deg, g->ukeys, g->optr, g->ocol, g->rank2id, g->id2rank, g->mlp, g->d_res, g->dq, g->tri};
     for (void *b : bufs)
-        if (b) (void)hipFreeAsync(b, g->stream);
-    (void)hipStreamSynchronize(g->stream);
+        kc_cache_free(b, g->stream);
+    (void)kc_sync(g->stream);
     delete[] g->dq_hist;
     for (hipEvent_t e : g->ev)
         if (e) (void)hipEventDestroy(e);
@@ -134,7 +132,7 @@ static kc_status create_impl(const uint32_t *src, const uint32_t *dst, uint64_t 
         dd = cd.as<uint32_t>();
     }
     KC_TRY(kc_canonicalise(g, ds, dd));
-    KC_HIP(hipStreamSynchronize(g->stream));
+    KC_TRY(kc_sync(g->stream));
     return KC_OK;
 }
 
@@ -254,7 +252,7 @@ kc_status kc_get_csr(const kc_graph *g, uint64_t *row_ptr, uint32_t *col, uint32
     if (row_ptr) KC_HIP(hipMemcpyAsync(row_ptr, g->rowptr, ((size_t)g->n + 1) * 8, hipMemcpyDeviceToDevice, s));
     if (col && g->m) KC_HIP(hipMemcpyAsync(col, g->col, 2 * (size_t)g->m * 4, hipMemcpyDeviceToDevice, s));
     if (deg) KC_HIP(hipMemcpyAsync(deg, g->deg, (size_t)g->n * 4, hipMemcpyDeviceToDevice, s));
-    KC_HIP(hipStreamSynchronize(s));
+    KC_TRY(kc_sync(s));
     return KC_OK;
 }
 
@@ -266,7 +264,7 @@ kc_status kc_get_oriented(const kc_graph *g, uint64_t *optr, uint32_t *ocol, uin
     if (optr) KC_HIP(hipMemcpyAsync(optr, g->optr, ((size_t)g->n + 1) * 8, hipMemcpyDeviceToDevice, s));
     if (ocol && g->m) KC_HIP(hipMemcpyAsync(ocol, g->ocol, (size_t)g->m * 4, hipMemcpyDeviceToDevice, s));
     if (rank2id) KC_HIP(hipMemcpyAsync(rank2id, g->rank2id, (size_t)g->n * 4, hipMemcpyDeviceToDevice, s));
-    KC_HIP(hipStreamSynchronize(s));
+    KC_TRY(kc_sync(s));
     return KC_OK;
 }
 

@@ -166,7 +166,7 @@ kc_status build_plan(kc_graph *const *gs, uint32_t num, int k, Plan &P) {
     KC_TRY(kc_scan_excl_u32(flag.as<uint32_t>(), pos.as<uint32_t>(), N, nullptr, s));
     uint32_t *h = (uint32_t *)kc_pinned_scratch();
     KC_HIP(hipMemcpyAsync(h, stats.p, 8 * 4, hipMemcpyDeviceToHost, s));
-    KC_HIP(hipStreamSynchronize(s));
+    KC_TRY(kc_sync(s));
     // key tiers: 0 scratch, 1 workgroup, 2 wave  ->  kc_queue tiers 2, 1, 0
     const uint32_t cs = h[0], cw = h[1], cv = h[2], total = cs + cw + cv;
     P.q.count[2] = cs;
@@ -206,7 +206,7 @@ kc_status run_plan(Plan &P, uint64_t *q_out) {
         KC_TRY(kc_count_launch(&P.bg, P.q, a, P.res.as<uint64_t>(), (unsigned long long *)P.gtot.p, P.num,
                                P.graph_of.as<uint32_t>(), P.gscr.as<uint64_t>(), P.slice_words, P.scratch_blocks, s));
         if (s && !P.eager_only) {
-            KC_HIP(hipStreamSynchronize(s));
+            KC_TRY(kc_sync(s));
             bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
             kc_status st = KC_OK;
             if (ok)
@@ -232,10 +232,10 @@ kc_status run_plan(Plan &P, uint64_t *q_out) {
         KC_HIP(hipGraphLaunch(P.exec, s));
     }
 
-    std::vector<uint64_t> res(2);
+    uint64_t *res = kc_pinned_scratch();
     KC_HIP(hipMemcpyAsync(q_out, P.gtot.p, (size_t)P.num * 8, hipMemcpyDeviceToHost, s));
-    KC_HIP(hipMemcpyAsync(res.data(), P.res.p, 16, hipMemcpyDeviceToHost, s));
-    KC_HIP(hipStreamSynchronize(s));
+    KC_HIP(hipMemcpyAsync(res, P.res.p, 16, hipMemcpyDeviceToHost, s));
+    KC_TRY(kc_sync(s));
     if (res[1]) return kc_fail(KC_EOVERFLOW, "a graph's count does not fit in 64 bits");
     return KC_OK;
 }
@@ -250,7 +250,7 @@ kc_status batch_impl(kc_graph *const *gs, uint32_t num, int32_t k, uint64_t *q_o
         if (!P) return kc_fail(KC_ENOMEM, "batch plan");
         kc_status st = build_plan(gs, num, k, *P);
         if (st != KC_OK) {
-            (void)hipStreamSynchronize(gs[0]->stream);
+            (void)kc_sync(gs[0]->stream);
             delete P;
             return st;
         }
@@ -295,7 +295,7 @@ void kc_batch_forget(uint64_t serial) {
     if (!g_plan) return;
     for (size_t i = 0; i + 5 < g_plan->key.size(); ++i)
         if (g_plan->key[i] == serial) {
-            (void)hipStreamSynchronize(g_plan->bg.stream);
+            (void)kc_sync(g_plan->bg.stream);
             delete g_plan;
             g_plan = nullptr;
             return;

@@ -1193,7 +1193,7 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
                            s, tev));
     uint64_t *h_res = kc_pinned_scratch();
     KC_HIP(hipMemcpyAsync(h_res, g->d_res, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    KC_HIP(hipStreamSynchronize(s));
+    KC_TRY(kc_sync(s));
     float t_sched = 0.f, t_count = 0.f, tt[3] = {0.f, 0.f, 0.f};
     (void)hipEventElapsedTime(&t_sched, g->ev[0], g->ev[1]);
     (void)hipEventElapsedTime(&t_count, g->ev[1], g->ev[5]);

@@ -149,10 +149,10 @@ kc_status kc_canonicalise(kc_graph *g, const uint32_t *d_src, const uint32_t *d_
         hipLaunchKernelGGL(k_make_keys, dim3(grid_for(g->m_in)), dim3(T), 0, s, d_src, d_dst, (size_t)g->m_in, n, B,
                            sentinel, keys.as<uint64_t>(), err.as<uint32_t>());
         KC_HIP(hipGetLastError());
-        uint32_t h_err = 0;
-        KC_HIP(hipMemcpyAsync(&h_err, err.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        KC_HIP(hipStreamSynchronize(s));
-        if (h_err) return kc_fail(KC_EINVAL, "an edge endpoint is >= n (%u)", n);
+        uint32_t *h = (uint32_t *)kc_pinned_scratch();
+        KC_HIP(hipMemcpyAsync(h, err.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        KC_TRY(kc_sync(s));
+        if (h[0]) return kc_fail(KC_EINVAL, "an edge endpoint is >= n (%u)", n);
         KC_TRY(kc_radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), N, 0, 2 * B, s));
         KC_TRY(kc_tmp_alloc(flag, N * sizeof(uint32_t), s));
         KC_TRY(kc_tmp_alloc(pos, N * sizeof(uint32_t), s));
@@ -160,8 +160,9 @@ kc_status kc_canonicalise(kc_graph *g, const uint32_t *d_src, const uint32_t *d_
                            flag.as<uint32_t>());
         KC_HIP(hipGetLastError());
         KC_TRY(kc_scan_excl_u32(flag.as<uint32_t>(), pos.as<uint32_t>(), N, total.as<uint32_t>(), s));
-        KC_HIP(hipMemcpyAsync(&M2, total.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        KC_HIP(hipStreamSynchronize(s));
+        KC_HIP(hipMemcpyAsync(h, total.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        KC_TRY(kc_sync(s));
+        M2 = h[0];
         // the unique keys stay on the handle until the orientation has used them
         KC_TRY(kc_dev_alloc((void **)&g->ukeys, (size_t)(M2 ? M2 : 1) * sizeof(uint64_t), s));
         hipLaunchKernelGGL(k_compact_u64, dim3(grid_for(N)), dim3(T), 0, s, keys.as<uint64_t>(), flag.as<uint32_t>(),
@@ -179,7 +180,7 @@ kc_status kc_canonicalise(kc_graph *g, const uint32_t *d_src, const uint32_t *d_
     hipLaunchKernelGGL(k_row_lengths, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)g->rowptr, n, g->deg,
                        (uint32_t *)nullptr);
     KC_HIP(hipGetLastError());
-    KC_HIP(hipStreamSynchronize(s));
+    KC_TRY(kc_sync(s));
     return KC_OK;
 }
 
@@ -234,10 +235,12 @@ kc_status kc_orient_impl(kc_graph *g) {
     hipLaunchKernelGGL(k_row_lengths, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)g->optr, n,
                        (uint32_t *)nullptr, maxd.as<uint32_t>());
     KC_HIP(hipGetLastError());
-    KC_HIP(hipMemcpyAsync(&g->max_outdeg, maxd.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    KC_HIP(hipStreamSynchronize(s));
+    uint32_t *h = (uint32_t *)kc_pinned_scratch();
+    KC_HIP(hipMemcpyAsync(h, maxd.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    KC_TRY(kc_sync(s));
+    g->max_outdeg = h[0];
     if (g->ukeys) {
-        KC_HIP(hipFreeAsync(g->ukeys, s));
+        kc_cache_free(g->ukeys, s);
         g->ukeys = nullptr;
     }
     g->oriented = 1;

@@ -25,25 +25,33 @@ kc_status kc_hip_fail(hipError_t e, const char *what, const char *file, int line
     } while (0)
 
 // ----------------------------------------------------------------------------
-// Stream-ordered temporary allocation (the device's default memory pool, with
-// its release threshold raised so that memory is reused across calls).
+// Device memory from the library's caching allocator (kc_alloc.hip): a block
+// freed on stream s is reused by later work on s at once, and by any stream
+// after kc_sync(s).
+kc_status kc_cache_alloc(void **p, size_t bytes, hipStream_t s);
+void kc_cache_free(void *p, hipStream_t s);
+// Host synchronisation of s; s's freed blocks become reusable on any stream.
+kc_status kc_sync(hipStream_t s);
+
+// Temporary buffer of one call, freed on its stream when it goes out of scope.
 struct kc_tmp {
     void *p = nullptr;
     hipStream_t s = nullptr;
     kc_tmp() = default;
     kc_tmp(const kc_tmp &) = delete;
     kc_tmp &operator=(const kc_tmp &) = delete;
-    ~kc_tmp() {
-        if (p) (void)hipFreeAsync(p, s);
-    }
+    ~kc_tmp() { kc_cache_free(p, s); }
     template <typename T>
     T *as() const { return static_cast<T *>(p); }
 };
 kc_status kc_tmp_alloc(kc_tmp &t, size_t bytes, hipStream_t s);
-// Stream-ordered allocation owned by a handle (freed with hipFreeAsync).
+// Allocation owned by a handle (released with kc_cache_free on its stream).
 kc_status kc_dev_alloc(void **p, size_t bytes, hipStream_t s);
 // A small pinned host buffer owned by the calling thread (512 bytes).
 uint64_t *kc_pinned_scratch();
+// A pinned host buffer of at least `bytes` owned by the calling thread (grown on
+// demand; the previous contents and pointer are invalid after a larger request).
+void *kc_pinned_buffer(size_t bytes);
 
 // ----------------------------------------------------------------------------
 // The handle.

@@ -216,7 +216,7 @@ kc_status ensure_tri(const kc_graph *g) {
     int ovf = 0;
     kc_status st = kc_count_impl(g, a, &total, &ovf);
     if (st != KC_OK) {
-        (void)hipFreeAsync(t, g->stream);
+        kc_cache_free(t, g->stream);
         return st;
     }
     gm->tri = t;
@@ -263,7 +263,7 @@ extern "C" kc_status kc_set_schedule(kc_graph *g, int32_t policy, const char *we
         if (!ok) return kc_fail(KC_EINVAL, "%s is not a scheduler weight file", weights_path);
         if (!g->mlp) KC_TRY(kc_dev_alloc((void **)&g->mlp, (NP + NORM) * 4, g->stream));
         KC_HIP(hipMemcpyAsync(g->mlp, buf.data(), (NP + NORM) * 4, hipMemcpyHostToDevice, g->stream));
-        KC_HIP(hipStreamSynchronize(g->stream));
+        KC_TRY(kc_sync(g->stream));
         g->mlp_loaded = 1;
     }
     if (policy == KC_SCHED_LEARNED && !g->mlp_loaded) return kc_fail(KC_ESTATE, "no scheduler weights loaded");
@@ -300,7 +300,7 @@ extern "C" kc_status kc_train_schedule(kc_graph *const *gs, uint32_t num, int32_
             KC_TRY(kc_scan_excl_u32(flag.as<uint32_t>(), pos.as<uint32_t>(), g->n, tot.as<uint32_t>(), g->stream));
             uint32_t na = 0;
             KC_HIP(hipMemcpyAsync(&na, tot.p, 4, hipMemcpyDeviceToHost, g->stream));
-            KC_HIP(hipStreamSynchronize(g->stream));
+            KC_TRY(kc_sync(g->stream));
             if (na == 0) continue;
             KC_TRY(kc_tmp_alloc(X, (size_t)na * NF * 4, g->stream));
             KC_TRY(kc_tmp_alloc(Tv, (size_t)na * 4, g->stream));
@@ -314,7 +314,7 @@ extern "C" kc_status kc_train_schedule(kc_graph *const *gs, uint32_t num, int32_
             hT.resize(o + na);
             KC_HIP(hipMemcpyAsync(hX.data() + o * NF, X.p, (size_t)na * NF * 4, hipMemcpyDeviceToHost, g->stream));
             KC_HIP(hipMemcpyAsync(hT.data() + o, Tv.p, (size_t)na * 4, hipMemcpyDeviceToHost, g->stream));
-            KC_HIP(hipStreamSynchronize(g->stream));
+            KC_TRY(kc_sync(g->stream));
         }
     }
     const size_t N = hT.size();
@@ -398,11 +398,11 @@ extern "C" kc_status kc_train_schedule(kc_graph *const *gs, uint32_t num, int32_
         }
         KC_HIP(hipGetLastError());
         KC_HIP(hipMemcpyAsync(&loss, dL.p, 4, hipMemcpyDeviceToHost, s));
-        KC_HIP(hipStreamSynchronize(s));
+        KC_TRY(kc_sync(s));
         loss = loss * (float)B / (float)N;  // mean over batches of the batch-mean loss, roughly
     }
     KC_HIP(hipMemcpyAsync(hp.data(), dP.p, NP * 4, hipMemcpyDeviceToHost, s));
-    KC_HIP(hipStreamSynchronize(s));
+    KC_TRY(kc_sync(s));
     FILE *f = fopen(weights_path, "wb");
     if (!f) return kc_fail(KC_EINVAL, "cannot write %s", weights_path);
     const uint32_t np = NP;

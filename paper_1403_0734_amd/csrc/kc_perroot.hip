@@ -55,12 +55,12 @@ extern "C" kc_status kc_count_per_root(const kc_graph *g, int32_t k, uint64_t *d
                                    (const uint64_t *)tmp.as<uint64_t>(), g->n, flag.as<uint32_t>());
                 KC_HIP(hipGetLastError());
             }
-            uint32_t h = 0;
-            KC_HIP(hipMemcpyAsync(&h, flag.p, 4, hipMemcpyDeviceToHost, s));
-            KC_HIP(hipStreamSynchronize(s));
-            if (h) return kc_fail(KC_EOVERFLOW, "work label overflows");
+            uint32_t *h = (uint32_t *)kc_pinned_scratch();
+            KC_HIP(hipMemcpyAsync(h, flag.p, 4, hipMemcpyDeviceToHost, s));
+            KC_TRY(kc_sync(s));
+            if (h[0]) return kc_fail(KC_EOVERFLOW, "work label overflows");
         }
     }
-    KC_HIP(hipStreamSynchronize(s));
+    KC_TRY(kc_sync(s));
     return KC_OK;
 }

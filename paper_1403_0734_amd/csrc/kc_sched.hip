@@ -127,7 +127,7 @@ __global__ void k_split_emit(const uint32_t *q, uint32_t cnt, const uint32_t *pa
 kc_status build_degree_cache(kc_graph *g, uint32_t wd) {
     hipStream_t s = g->stream;
     if (g->dq) {
-        KC_HIP(hipFreeAsync(g->dq, s));
+        kc_cache_free(g->dq, s);
         g->dq = nullptr;
     }
     delete[] g->dq_hist;
@@ -147,23 +147,19 @@ kc_status build_degree_cache(kc_graph *g, uint32_t wd) {
                        keys.as<uint64_t>(), flag.as<uint32_t>(), hist.as<uint32_t>());
     KC_HIP(hipGetLastError());
     KC_TRY(kc_scan_excl_u32(flag.as<uint32_t>(), pos.as<uint32_t>(), n, total.as<uint32_t>(), s));
-    uint32_t *h = new (std::nothrow) uint32_t[hn + 1];
-    if (!h) return kc_fail(KC_ENOMEM, "host histogram");
-    uint32_t active = 0;
+    uint32_t *h = (uint32_t *)kc_pinned_buffer(((size_t)hn + 1) * 4);
+    if (!h) return kc_fail(KC_ENOMEM, "pinned host histogram");
     KC_HIP(hipMemcpyAsync(h, hist.p, (size_t)hn * 4, hipMemcpyDeviceToHost, s));
-    KC_HIP(hipMemcpyAsync(&active, total.p, 4, hipMemcpyDeviceToHost, s));
-    KC_HIP(hipStreamSynchronize(s));
+    KC_HIP(hipMemcpyAsync(h + hn, total.p, 4, hipMemcpyDeviceToHost, s));
+    KC_TRY(kc_sync(s));
+    const uint32_t active = h[hn];
     g->dq_hist = new (std::nothrow) uint64_t[hn];
-    if (!g->dq_hist) {
-        delete[] h;
-        return kc_fail(KC_ENOMEM, "host histogram");
-    }
+    if (!g->dq_hist) return kc_fail(KC_ENOMEM, "host histogram");
     uint32_t wide = 0;
     for (uint32_t d = 0; d < hn; ++d) {
         g->dq_hist[d] = h[d];
         if (d > wd) wide += h[d];
     }
-    delete[] h;
     g->dq_wide = wide;
     g->dq_narrow = active - wide;
     KC_TRY(kc_dev_alloc((void **)&g->dq, (size_t)(active ? active : 1) * 4, s));
@@ -246,7 +242,7 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
     KC_TRY(kc_scan_excl_u32(flag.as<uint32_t>(), pos.as<uint32_t>(), n, nullptr, s));
     uint32_t *h_stats = (uint32_t *)kc_pinned_scratch();
     KC_HIP(hipMemcpyAsync(h_stats, stats.p, 8 * 4, hipMemcpyDeviceToHost, s));
-    KC_HIP(hipStreamSynchronize(s));
+    KC_TRY(kc_sync(s));
     const uint32_t total = h_stats[0] + h_stats[1] + h_stats[2];
     uint32_t off = 0;
     for (int t = 0; t < 3; ++t) {
@@ -286,9 +282,10 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
                            (const float *)pred.as<float>(), (const double *)sum.as<double>(), per, 64u,
                            parts.as<uint32_t>());
         KC_TRY(kc_scan_excl_u32(parts.as<uint32_t>(), offs.as<uint32_t>(), c1, ntot.as<uint32_t>(), s));
-        uint32_t nitems = 0;
-        KC_HIP(hipMemcpyAsync(&nitems, ntot.p, 4, hipMemcpyDeviceToHost, s));
-        KC_HIP(hipStreamSynchronize(s));
+        uint32_t *hn = (uint32_t *)kc_pinned_scratch();
+        KC_HIP(hipMemcpyAsync(hn, ntot.p, 4, hipMemcpyDeviceToHost, s));
+        KC_TRY(kc_sync(s));
+        const uint32_t nitems = hn[0];
         KC_TRY(kc_tmp_alloc(q.items_buf, (size_t)nitems * 8, s));
         hipLaunchKernelGGL(k_split_emit, dim3(grid_for(c1)), dim3(T), 0, s, q.ptr[1], c1,
                            (const uint32_t *)parts.as<uint32_t>(), (const uint32_t *)offs.as<uint32_t>(),
