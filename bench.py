@@ -49,6 +49,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batch (512 graphs, k=5) and schedule-comparison (planted 4M, k=3..8) sections")
     ap.add_argument("--batch-graphs", type=int, default=512)
+    ap.add_argument("--tuning", default=None, metavar="WD,WGB,WVB,CD",
+                    help="launch tunables for the timed steps (default: the library's)")
     ap.add_argument("--sched-ks", default="3,4,5,6,7,8")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE) and exit")
@@ -89,6 +91,8 @@ def main():
     stream = torch.cuda.current_stream().cuda_stream
     torch.cuda.synchronize()
     lib = K.load()
+    if args.tuning:
+        K.kc_set_tuning(*[int(x) for x in args.tuning.split(",")])
     policy = K.KC_SCHED_LEARNED if args.schedule == "learned" else K.KC_SCHED_DEGREE
 
     def step(record=None):

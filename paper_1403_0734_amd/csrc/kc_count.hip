@@ -363,7 +363,7 @@ struct WaveStage {
     uint32_t filt[64];  // 2048-bit membership filter of the packed Gamma+ lists
     uint32_t qy[128];   // ring of filter survivors: out-list element ...
     uint8_t qi[128];    // ... and the list (local node) it came from
-    uint8_t flag[64];   // per 64-element window: 1 + list starting at each slot
+    uint8_t flag[128];  // per 128-element step: 1 + list starting at each slot
 };
 static_assert(sizeof(WaveStage) <= sizeof(LocalArea<1>), "staging overlay must fit the local-graph area");
 
@@ -502,6 +502,7 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
         sm.A.rows[lane] = 0;
         sm.S.filt[lane] = 0;
         sm.S.flag[lane] = 0;
+        sm.S.flag[64 + lane] = 0;
         const bool percol = p.colored && p.scheme == KC_COLOR_PER_ROOT;
         if (percol) sm.colr[lane] = lane < d ? root_colour(p.seed, p.rank2id[u], p.rank2id[a], p.c) : 0u;
         wave_sync();
@@ -517,35 +518,46 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
         // and a ballot); the filter drops most non-members, the rest queue up
         // for an exact search 64 at a time.
         uint32_t carry = 0, qh = 0, qt = 0;
-        for (uint32_t w0 = 0; w0 < Ttot; w0 += 64) {
-            if (len && excl >= w0 && excl - w0 < 64u) sm.S.flag[excl - w0] = (uint8_t)(lane + 1u);
+        // two windows per step, so that each lane has two loads in flight
+        const uint64_t le_mask = kc_lanemask_lt() | (1ull << lane);
+        for (uint32_t w0 = 0; w0 < Ttot; w0 += 128) {
+            if (len && excl >= w0 && excl - w0 < 128u) sm.S.flag[excl - w0] = (uint8_t)(lane + 1u);
             wave_sync();
-            const uint32_t f = sm.S.flag[lane];
-            const uint64_t le = __ballot(f != 0) & (kc_lanemask_lt() | (1ull << lane));
-            const uint32_t fo = __shfl(f, le ? 63u - (uint32_t)__builtin_clzll(le) : 0u, 64);
-            const uint32_t i = le ? fo - 1u : carry;
-            carry = __shfl(i, 63, 64);
-            if (f) sm.S.flag[lane] = 0;
-            const uint32_t e = w0 + lane;
-            bool keep = false;
-            uint32_t y = 0;
-            if (e < Ttot) {
-                y = p.ocol[sm.delta[i] + e];
-                const uint32_t h = filt_hash(y);
-                keep = (sm.S.filt[h >> 5] >> (h & 31u)) & 1u;
-            }
-            const uint64_t kb = __ballot(keep);
-            if (keep) {
-                const uint32_t slot = (qt + (uint32_t)__popcll(kb & kc_lanemask_lt())) & 127u;
-                sm.S.qy[slot] = y;
-                sm.S.qi[slot] = (uint8_t)i;
-            }
-            qt += (uint32_t)__popcll(kb);
-            if (qt - qh >= 64u) {
-                wave_sync();
-                wave_stage_check(sm, qh, 64u, percol);
-                qh += 64u;
-                wave_sync();
+            const uint32_t f0 = sm.S.flag[lane], f1 = sm.S.flag[64 + lane];
+            const uint64_t le0 = __ballot(f0 != 0) & le_mask, le1 = __ballot(f1 != 0) & le_mask;
+            const uint32_t fo0 = __shfl(f0, le0 ? 63u - (uint32_t)__builtin_clzll(le0) : 0u, 64);
+            const uint32_t fo1 = __shfl(f1, le1 ? 63u - (uint32_t)__builtin_clzll(le1) : 0u, 64);
+            const uint32_t i0 = le0 ? fo0 - 1u : carry;
+            const uint32_t c1 = __shfl(i0, 63, 64);
+            const uint32_t i1 = le1 ? fo1 - 1u : c1;
+            carry = __shfl(i1, 63, 64);
+            if (f0) sm.S.flag[lane] = 0;
+            if (f1) sm.S.flag[64 + lane] = 0;
+            const uint32_t e0 = w0 + lane, e1 = w0 + 64u + lane;
+            uint32_t y0 = 0, y1 = 0;
+            if (e0 < Ttot) y0 = p.ocol[sm.delta[i0] + e0];
+            if (e1 < Ttot) y1 = p.ocol[sm.delta[i1] + e1];
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf) {
+                const uint32_t y = hf ? y1 : y0, i = hf ? i1 : i0;
+                bool keep = false;
+                if ((hf ? e1 : e0) < Ttot) {
+                    const uint32_t h = filt_hash(y);
+                    keep = (sm.S.filt[h >> 5] >> (h & 31u)) & 1u;
+                }
+                const uint64_t kb = __ballot(keep);
+                if (keep) {
+                    const uint32_t slot = (qt + (uint32_t)__popcll(kb & kc_lanemask_lt())) & 127u;
+                    sm.S.qy[slot] = y;
+                    sm.S.qi[slot] = (uint8_t)i;
+                }
+                qt += (uint32_t)__popcll(kb);
+                if (qt - qh >= 64u) {
+                    wave_sync();
+                    wave_stage_check(sm, qh, 64u, percol);
+                    qh += 64u;
+                    wave_sync();
+                }
             }
         }
         if (qt != qh) {
@@ -893,34 +905,29 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
             // q_{u,2} = edges of G+(u) = set bits of the whole bitmap
             for (uint64_t w = tid; w < words; w += WG) acc += (uint64_t)__popcll(bm[w]);
         } else {
-            // first-level nodes, one per wave at a time; a root split into `parts`
-            // items (Section 7: heavy G+(u) shared by several reducers) takes the
-            // nodes part, part + parts, part + 2 parts, ... in this item
-            for (;;) {
-                uint32_t j = 0;
-                if (lane == 0) j = atomicAdd(&s_misc[2], 1u);
-                j = __shfl(j, 0, 64);
-                const uint32_t i = part + j * parts;
-                if (i >= d) break;
+            // first-level nodes; a root split into `parts` items (Section 7: heavy
+            // G+(u) shared by several reducers) takes the nodes part, part + parts,
+            // part + 2 parts, ... in this item.  One node with a whole wave:
+            auto one_node = [&](const uint32_t i) {
                 const uint32_t lo0 = (i + 1) >> 6;
                 const uint64_t *ri = bm_row(bm, i, W);
                 uint32_t pc = 0;
                 for (uint32_t l = lo0 + lane; l < W; l += 64) pc += (uint32_t)__popcll(ri[l]);
                 pc = kc_wave_sum_u32(pc);
-                if ((int)pc < K - 2) continue;
+                if ((int)pc < K - 2) return;
                 if (K == 4) {
                     wide_edges(ri, lo0, W, bm, acc);
-                    continue;
+                    return;
                 }
                 if (pc <= 64) {
                     const uint32_t sN = compact_local(ri, lo0, W, bm, W, idxmap, A);
                     local_count(A, sN, K - 2, acc);
-                    continue;
+                    return;
                 }
                 if (K >= 5 && pc <= 128) {
                     const uint32_t sN = compact_local2(ri, lo0, W, bm, W, idxmap, A2);
                     local_count2(A2, sN, K - 2, acc);
-                    continue;
+                    return;
                 }
                 // Wide depth-first search.  stk[depth] holds the candidates not yet
                 // visited of a node that still needs K-2-depth nodes; a child that
@@ -979,6 +986,100 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                         ++depth;
                         lo[depth] = clo;
                     }
+                }
+            };
+            if (K >= 5) {
+                // Nodes are taken GRAB at a time.  Those with more than 64 candidates
+                // go one by one; the others are packed while their candidate sets
+                // sum to at most 64 nodes, side by side as the diagonal blocks of one
+                // local graph (no edge joins two blocks), counted in one pass.
+                constexpr uint32_t GRAB = 16;
+                uint8_t *rs = reinterpret_cast<uint8_t *>(&A.members[0]);  // block starts
+                uint8_t *rt = rs + 64;                                      // block's slot in the grab
+                for (;;) {
+                    uint32_t j0 = 0;
+                    if (lane == 0) j0 = atomicAdd(&s_misc[2], GRAB);
+                    j0 = __shfl(j0, 0, 64);
+                    if (part + j0 * parts >= d) break;
+                    const uint32_t my_i = part + (j0 + lane) * parts;
+                    const bool valid = lane < GRAB && my_i < d;
+                    uint32_t my_pc = 0;
+                    if (valid) {
+                        const uint64_t *ri = bm_row(bm, my_i, W);
+                        for (uint32_t l = (my_i + 1) >> 6; l < W; ++l) my_pc += (uint32_t)__popcll(ri[l]);
+                    }
+                    uint64_t big = __ballot(valid && my_pc > 64u);
+                    while (big) {
+                        const uint32_t t = (uint32_t)__builtin_ctzll(big);
+                        big &= big - 1;
+                        one_node(__shfl(my_i, t, 64));
+                    }
+                    uint64_t cm = __ballot(valid && my_pc >= (uint32_t)(K - 2) && my_pc <= 64u);
+                    while (cm) {
+                        const bool in = (cm >> lane) & 1ull;
+                        const uint32_t v = in ? my_pc : 0u;
+                        const uint32_t incl = kc_wave_incl_u32(v);
+                        const uint64_t fit = __ballot(in && incl <= 64u);
+                        const uint32_t S = __shfl(incl, 63u - (uint32_t)__builtin_clzll(fit), 64);
+                        const uint32_t g = (uint32_t)__popcll(fit);
+                        if ((fit >> lane) & 1ull) {
+                            const uint32_t r = (uint32_t)__popcll(fit & kc_lanemask_lt());
+                            rs[r] = (uint8_t)(incl - v);
+                            rt[r] = (uint8_t)lane;
+                        }
+                        wave_sync();
+                        uint64_t lrow = 0;
+                        if (lane < S) {
+                            uint32_t r = 0, hi = g;  // last block starting at or before this lane
+                            while (hi - r > 1) {
+                                const uint32_t mid = (r + hi) >> 1;
+                                if (rs[mid] <= lane) r = mid; else hi = mid;
+                            }
+                            const uint32_t base = rs[r];
+                            const uint32_t i = part + (j0 + rt[r]) * parts;
+                            const uint32_t lo0 = (i + 1) >> 6;
+                            const uint64_t *ri = bm_row(bm, i, W);
+                            // member: the (lane - base)-th node of row i
+                            uint32_t rem = lane - base, l = lo0;
+                            uint64_t w = ri[l];
+                            for (;;) {
+                                const uint32_t c = (uint32_t)__popcll(w);
+                                if (rem < c) break;
+                                rem -= c;
+                                w = ri[++l];
+                            }
+                            const uint32_t vn = 64 * l + select_bit(w, rem);
+                            // its row inside row i, renumbered by rank in row i
+                            const uint64_t *rv = bm_row(bm, vn, W);
+                            const uint32_t vlo = (vn + 1) >> 6;
+                            uint32_t run = base;
+                            for (uint32_t l2 = lo0; l2 < W; ++l2) {
+                                const uint64_t pw = ri[l2];
+                                if (l2 >= vlo) {
+                                    uint64_t x = rv[l2] & pw;
+                                    while (x) {
+                                        const uint32_t bpos = (uint32_t)__builtin_ctzll(x);
+                                        x &= x - 1;
+                                        lrow |= 1ull << (run + (uint32_t)__popcll(pw & ((1ull << bpos) - 1ull)));
+                                    }
+                                }
+                                run += (uint32_t)__popcll(pw);
+                            }
+                        }
+                        A.rows[lane] = lrow;
+                        wave_sync();
+                        local_count(A, S, K - 2, acc);
+                        cm &= ~fit;
+                    }
+                }
+            } else {
+                for (;;) {
+                    uint32_t j = 0;
+                    if (lane == 0) j = atomicAdd(&s_misc[2], 1u);
+                    j = __shfl(j, 0, 64);
+                    const uint32_t i = part + j * parts;
+                    if (i >= d) break;
+                    one_node(i);
                 }
             }
         }
