@@ -49,15 +49,23 @@ __global__ void k_compact_u64(const uint64_t *in, const uint32_t *flag, const ui
 }
 
 // Row pointers of a CSR given its keys sorted by row (row = key >> B):
-// rowptr[r] = first position whose row is >= r, rowptr[n] = M.
+// rowptr[r] = first position whose row is >= r (a binary search per row, so
+// that runs of empty rows cost nothing extra), rowptr[n] = M.
 __global__ void k_rowptr(const uint64_t *keys, size_t M, int B, uint32_t n, uint64_t *rowptr) {
-    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= M) return;
-    const int64_t r = (int64_t)(keys[p] >> B);
-    const int64_t rp = p == 0 ? -1 : (int64_t)(keys[p - 1] >> B);
-    for (int64_t x = rp + 1; x <= r; ++x) rowptr[x] = p;
-    if (p == M - 1)
-        for (int64_t x = r + 1; x <= (int64_t)n; ++x) rowptr[x] = M;
+    const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > n) return;
+    const uint64_t key = (uint64_t)r << B;
+    size_t lo = 0, len = M;
+    while (len > 0) {
+        const size_t half = len >> 1;
+        if (keys[lo + half] < key) {
+            lo += half + 1;
+            len -= half + 1;
+        } else {
+            len = half;
+        }
+    }
+    rowptr[r] = lo;
 }
 
 __global__ void k_fill_u64(uint64_t *p, size_t n, uint64_t v) {
@@ -70,17 +78,29 @@ __global__ void k_low_bits(const uint64_t *keys, size_t M, uint64_t mask, uint32
     if (p < M) out[p] = (uint32_t)(keys[p] & mask);
 }
 
+// Row lengths (optional) and their maximum (optional): grid-stride, one atomic per block.
 __global__ void k_row_lengths(const uint64_t *rowptr, uint32_t n, uint32_t *len, uint32_t *maxlen) {
-    const size_t x = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t l = 0;
-    if (x < n) {
-        l = (uint32_t)(rowptr[x + 1] - rowptr[x]);
+    __shared__ uint32_t s_max[T / 64];
+    uint32_t mx = 0;
+    for (size_t x = (size_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t l = (uint32_t)(rowptr[x + 1] - rowptr[x]);
         if (len) len[x] = l;
+        mx = l > mx ? l : mx;
     }
     if (maxlen) {
-        l = kc_wave_max_u32(l);
-        if ((threadIdx.x & 63) == 0) atomicMax(maxlen, l);
+        mx = kc_wave_max_u32(mx);
+        if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = mx;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < T / 64; ++w) mx = s_max[w] > mx ? s_max[w] : mx;
+            atomicMax(maxlen, mx);
+        }
     }
+}
+constexpr unsigned ROWLEN_BLOCKS = 1024;
+inline unsigned rowlen_grid(uint32_t n) {
+    const unsigned g = grid_for(n);
+    return g < ROWLEN_BLOCKS ? (g ? g : 1u) : ROWLEN_BLOCKS;
 }
 
 // node key (d(x), x): the paper's order as one integer
@@ -119,7 +139,7 @@ kc_status rows_from_sorted(const uint64_t *keys, size_t M, int B, uint32_t n, ui
     if (M == 0) {
         hipLaunchKernelGGL(k_fill_u64, dim3(grid_for((size_t)n + 1)), dim3(T), 0, s, rowptr, (size_t)n + 1, 0ull);
     } else {
-        hipLaunchKernelGGL(k_rowptr, dim3(grid_for(M)), dim3(T), 0, s, keys, M, B, n, rowptr);
+        hipLaunchKernelGGL(k_rowptr, dim3(grid_for((size_t)n + 1)), dim3(T), 0, s, keys, M, B, n, rowptr);
     }
     KC_HIP(hipGetLastError());
     return KC_OK;
@@ -177,7 +197,7 @@ kc_status kc_canonicalise(kc_graph *g, const uint32_t *d_src, const uint32_t *d_
         hipLaunchKernelGGL(k_low_bits, dim3(grid_for(M2)), dim3(T), 0, s, uk, (size_t)M2, mask, g->col);
         KC_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_row_lengths, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)g->rowptr, n, g->deg,
+    hipLaunchKernelGGL(k_row_lengths, dim3(rowlen_grid(n)), dim3(T), 0, s, (const uint64_t *)g->rowptr, n, g->deg,
                        (uint32_t *)nullptr);
     KC_HIP(hipGetLastError());
     KC_TRY(kc_sync(s));
@@ -232,7 +252,7 @@ kc_status kc_orient_impl(kc_graph *g) {
         KC_HIP(hipGetLastError());
     }
     KC_TRY(rows_from_sorted(okeys.as<uint64_t>(), m, B, n, g->optr, s));
-    hipLaunchKernelGGL(k_row_lengths, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)g->optr, n,
+    hipLaunchKernelGGL(k_row_lengths, dim3(rowlen_grid(n)), dim3(T), 0, s, (const uint64_t *)g->optr, n,
                        (uint32_t *)nullptr, maxd.as<uint32_t>());
     KC_HIP(hipGetLastError());
     uint32_t *h = (uint32_t *)kc_pinned_scratch();

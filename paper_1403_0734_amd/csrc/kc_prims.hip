@@ -128,12 +128,29 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const uint64_t *keys, si
     hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = s_h[threadIdx.x];
 }
 
+// Stable scatter of one tile: keys are first ranked and placed in LDS in digit
+// order (tile-local start of each digit from this tile's histogram), then
+// written out in that order, so that each digit's keys of the tile leave as
+// one contiguous run.
 __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint64_t *in, uint64_t *out, size_t n, int shift,
-                                                           const uint32_t *offs, uint32_t nblocks) {
-    __shared__ uint32_t s_base[256];
+                                                           const uint32_t *hist, const uint32_t *offs,
+                                                           uint32_t nblocks) {
+    __shared__ uint64_t s_keys[RS_TILE];
+    __shared__ uint32_t s_start[256];  // tile-local first position of each digit
+    __shared__ uint32_t s_run[256];    // keys of each digit placed so far
+    __shared__ uint32_t s_gbase[256];  // global first position of each digit's run
     __shared__ uint32_t s_w[RS_THREADS / 64][256];
+    __shared__ uint32_t s_wt[RS_THREADS / 64];
     const int tid = threadIdx.x, wave = tid >> 6;
-    s_base[tid] = offs[(size_t)tid * nblocks + blockIdx.x];
+    const uint32_t c = hist[(size_t)tid * nblocks + blockIdx.x];
+    const uint32_t inc = kc_wave_incl_u32(c);
+    if ((tid & 63) == 63) s_wt[wave] = inc;
+    s_gbase[tid] = offs[(size_t)tid * nblocks + blockIdx.x];
+    s_run[tid] = 0;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += s_wt[w];
+    s_start[tid] = before + inc - c;
     const size_t base = (size_t)blockIdx.x * RS_TILE;
     for (int r = 0; r < RS_ITEMS; ++r) {
         const size_t i = base + (size_t)r * RS_THREADS + tid;
@@ -148,15 +165,23 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint64_t *in, u
         if (valid && lower == 0) s_w[wave][d] = (uint32_t)__popcll(peers);
         __syncthreads();
         if (valid) {
-            uint32_t off = s_base[d] + (uint32_t)__popcll(lower);
+            uint32_t off = s_start[d] + s_run[d] + (uint32_t)__popcll(lower);
             for (int w = 0; w < wave; ++w) off += s_w[w][d];
-            out[off] = key;
+            s_keys[off] = key;
         }
         __syncthreads();
         uint32_t add = 0;
 #pragma unroll
         for (int w = 0; w < RS_THREADS / 64; ++w) add += s_w[w][tid];
-        s_base[tid] += add;
+        s_run[tid] += add;
+    }
+    __syncthreads();
+    const size_t left = n - base;
+    const uint32_t tile_n = left < (size_t)RS_TILE ? (uint32_t)left : (uint32_t)RS_TILE;
+    for (uint32_t q = tid; q < tile_n; q += RS_THREADS) {
+        const uint64_t key = s_keys[q];
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        out[(size_t)s_gbase[d] + (q - s_start[d])] = key;
     }
 }
 
@@ -184,7 +209,8 @@ kc_status kc_radix_sort_u64(uint64_t *keys, uint64_t *tmp, size_t n, int bit_lo,
         KC_HIP(hipGetLastError());
         KC_TRY(kc_scan_excl_u32(hist.as<uint32_t>(), offs.as<uint32_t>(), (size_t)256 * nblocks, nullptr, s));
         hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(RS_THREADS), 0, s, (const uint64_t *)src, dst, n,
-                           shift, (const uint32_t *)offs.as<uint32_t>(), nblocks);
+                           shift, (const uint32_t *)hist.as<uint32_t>(), (const uint32_t *)offs.as<uint32_t>(),
+                           nblocks);
         KC_HIP(hipGetLastError());
         uint64_t *t = src;
         src = dst;
