@@ -125,7 +125,7 @@ kc_status build_plan(kc_graph *const *gs, uint32_t num, int k, Plan &P) {
     KC_TRY(kc_tmp_alloc(P.ocol, (M ? M : 1) * 4, s));
     KC_TRY(kc_tmp_alloc(P.graph_of, (N ? N : 1) * 4, s));
     KC_TRY(kc_tmp_alloc(P.gtot, (size_t)num * 8, s));
-    KC_TRY(kc_tmp_alloc(P.res, 8 * 8, s));
+    KC_TRY(kc_tmp_alloc(P.res, KC_RES_WORDS * 8, s));
     bg.optr = P.optr.as<uint64_t>();
     bg.ocol = P.ocol.as<uint32_t>();
     bg.rank2id = nullptr;  // exact totals only: ids are never read

@@ -633,7 +633,7 @@ __host__ __device__ inline size_t wg_static_lds(int K) { return wg_local_bytes(K
 // Layout of one workgroup's arena (LDS, or a global slice for the scratch tier)
 // for out-degree cap D and clique size K.
 struct WgLayout {
-    size_t nb, seg, colr, delta, stk, idx, htab, bm, bytes;
+    size_t nb, seg, colr, delta, stk, htab, bm, bytes;
     uint32_t W, hbits;
 };
 __host__ __device__ inline WgLayout wg_layout(uint32_t D, int K) {
@@ -645,7 +645,6 @@ __host__ __device__ inline WgLayout wg_layout(uint32_t D, int K) {
     L.nb = o;    o += (size_t)D * 4;
     L.seg = o;   o += ((size_t)D + 1) * 4;
     L.colr = o;  o += (size_t)D * 4;
-    L.idx = o;   o += (size_t)WAVES * D;  // local index of each bit, per wave
     o = (o + 3) & ~(size_t)3;
     L.hbits = hash_bits(D);
     // the table lives in the per-wave local-graph areas (idle while staging) when it fits
@@ -664,37 +663,44 @@ __device__ __forceinline__ const uint64_t *bm_row(const uint64_t *bm, uint32_t i
     return bm + tri_rowoff(i, W) - ((i + 1) >> 6);  // indexed by absolute word number
 }
 
+// Local index of the node at bit b of word l of a node set P: the members are
+// numbered in ascending order, so it is the number of members before it.
+// `run` holds the members in words lo..l-1.
+__device__ __forceinline__ uint32_t member_rank(uint64_t pw, uint32_t b, uint32_t run) {
+    return run + (uint32_t)__popcll(pw & ((1ull << b) - 1ull));
+}
+
 // Compact the node set P (words lo..W-1, absolute word index) of at most 64
-// nodes into A: member t = t-th node of P, local row t = its row restricted to P.
-// Returns the number of members.
+// nodes into A: member t = t-th node of P, local row t = its row restricted to P
+// (bits renumbered by member rank, arithmetic only).  Returns the number of members.
 template <class Area>
 __device__ __forceinline__ uint32_t compact_local(const uint64_t *P, uint32_t lo, uint32_t W, const uint64_t *bm,
-                                                  uint32_t Wbm, uint8_t *idx, Area &A) {
+                                                  uint32_t Wbm, Area &A) {
     const uint32_t lane = kc_lane();
     uint32_t nmem = 0;
     for (uint32_t l = lo; l < W; ++l) {
         const uint64_t word = P[l];
-        const bool bit = (word >> lane) & 1ull;
-        const uint64_t bal = __ballot(bit);
-        if (bit) {
-            const uint32_t li = nmem + (uint32_t)__popcll(bal & kc_lanemask_lt());
-            idx[64 * l + lane] = (uint8_t)li;
-            A.members[li] = 64 * l + lane;
-        }
-        nmem += (uint32_t)__popcll(bal);
+        if ((word >> lane) & 1ull) A.members[nmem + (uint32_t)__popcll(word & kc_lanemask_lt())] = 64 * l + lane;
+        nmem += (uint32_t)__popcll(word);
     }
     wave_sync();
     uint64_t lrow = 0;
     if (lane < nmem) {
         const uint32_t v = A.members[lane];
         const uint64_t *rv = bm_row(bm, v, Wbm);
-        for (uint32_t l = (v + 1) >> 6; l < W; ++l) {
-            uint64_t x = rv[l] & P[l];
-            while (x) {
-                const uint32_t b = (uint32_t)__builtin_ctzll(x);
-                x &= x - 1;
-                lrow |= 1ull << idx[64 * l + b];
+        const uint32_t vlo = (v + 1) >> 6;
+        uint32_t run = 0;
+        for (uint32_t l = lo; l < W; ++l) {
+            const uint64_t pw = P[l];
+            if (l >= vlo) {
+                uint64_t x = rv[l] & pw;
+                while (x) {
+                    const uint32_t b = (uint32_t)__builtin_ctzll(x);
+                    x &= x - 1;
+                    lrow |= 1ull << member_rank(pw, b, run);
+                }
             }
+            run += (uint32_t)__popcll(pw);
         }
     }
     A.rows[lane] = lrow;
@@ -705,19 +711,13 @@ __device__ __forceinline__ uint32_t compact_local(const uint64_t *P, uint32_t lo
 // As compact_local, for a node set of at most 128 nodes into a two-word local graph.
 template <class Area>
 __device__ __forceinline__ uint32_t compact_local2(const uint64_t *P, uint32_t lo, uint32_t W, const uint64_t *bm,
-                                                   uint32_t Wbm, uint8_t *idx, Area &A) {
+                                                   uint32_t Wbm, Area &A) {
     const uint32_t lane = kc_lane();
     uint32_t nmem = 0;
     for (uint32_t l = lo; l < W; ++l) {
         const uint64_t word = P[l];
-        const bool bit = (word >> lane) & 1ull;
-        const uint64_t bal = __ballot(bit);
-        if (bit) {
-            const uint32_t li = nmem + (uint32_t)__popcll(bal & kc_lanemask_lt());
-            idx[64 * l + lane] = (uint8_t)li;
-            A.members[li] = 64 * l + lane;
-        }
-        nmem += (uint32_t)__popcll(bal);
+        if ((word >> lane) & 1ull) A.members[nmem + (uint32_t)__popcll(word & kc_lanemask_lt())] = 64 * l + lane;
+        nmem += (uint32_t)__popcll(word);
     }
     wave_sync();
     for (uint32_t half = 0; half < 2; ++half) {
@@ -726,15 +726,21 @@ __device__ __forceinline__ uint32_t compact_local2(const uint64_t *P, uint32_t l
         if (t < nmem) {
             const uint32_t v = A.members[t];
             const uint64_t *rv = bm_row(bm, v, Wbm);
-            for (uint32_t l = (v + 1) >> 6; l < W; ++l) {
-                uint64_t x = rv[l] & P[l];
-                while (x) {
-                    const uint32_t b = (uint32_t)__builtin_ctzll(x);
-                    x &= x - 1;
-                    const uint32_t li = idx[64 * l + b];
-                    if (li < 64) l0 |= 1ull << li;
-                    else l1 |= 1ull << (li - 64);
+            const uint32_t vlo = (v + 1) >> 6;
+            uint32_t run = 0;
+            for (uint32_t l = lo; l < W; ++l) {
+                const uint64_t pw = P[l];
+                if (l >= vlo) {
+                    uint64_t x = rv[l] & pw;
+                    while (x) {
+                        const uint32_t b = (uint32_t)__builtin_ctzll(x);
+                        x &= x - 1;
+                        const uint32_t li = member_rank(pw, b, run);
+                        if (li < 64) l0 |= 1ull << li;
+                        else l1 |= 1ull << (li - 64);
+                    }
                 }
+                run += (uint32_t)__popcll(pw);
             }
         }
         A.rows[t][0] = l0;
@@ -745,18 +751,37 @@ __device__ __forceinline__ uint32_t compact_local2(const uint64_t *P, uint32_t l
 }
 
 // Edges of G+(u) inside the node set C (words lo..W-1, absolute word index):
-// sum over members v of |C n row_v|, one member per lane, 64 members per round.
+// sum over members v of |C n row_v|.  Members are gathered 64 at a time into
+// mem (one per lane), each lane then intersects its member's row with C.
 __device__ __forceinline__ void wide_edges(const uint64_t *C, uint32_t lo, uint32_t W, const uint64_t *bm,
-                                           uint64_t &acc) {
+                                           uint32_t *mem, uint64_t &acc) {
     const uint32_t lane = kc_lane();
-    for (uint32_t wb = lo; wb < W; ++wb) {
-        const uint64_t word = C[wb];
-        if ((word >> lane) & 1ull) {
-            const uint32_t v = 64 * wb + lane;
+    auto flush = [&](uint32_t k) {
+        wave_sync();
+        if (lane < k) {
+            const uint32_t v = mem[lane];
             const uint64_t *rv = bm_row(bm, v, W);
             for (uint32_t l = (v + 1) >> 6; l < W; ++l) acc += (uint64_t)__popcll(rv[l] & C[l]);
         }
+        wave_sync();
+    };
+    uint32_t cnt = 0;
+    for (uint32_t wb = lo; wb < W; ++wb) {
+        const uint64_t word = C[wb];
+        if (!word) continue;
+        const uint32_t nbits = (uint32_t)__popcll(word);
+        const bool bit = (word >> lane) & 1ull;
+        const uint32_t rk = cnt + (uint32_t)__popcll(word & kc_lanemask_lt());
+        if (bit && rk < 64) mem[rk] = 64 * wb + lane;
+        if (cnt + nbits >= 64) {
+            flush(64);
+            if (bit && rk >= 64) mem[rk - 64] = 64 * wb + lane;
+            cnt = cnt + nbits - 64;
+        } else {
+            cnt += nbits;
+        }
     }
+    if (cnt) flush(cnt);
 }
 
 template <int K, bool GLOBAL>
@@ -780,7 +805,6 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
     const uint32_t Wc = L.W;
     const int levels = K > 3 ? K - 3 : 1;
     uint64_t *stk = (uint64_t *)(arena + L.stk) + (size_t)wave * levels * Wc;
-    uint8_t *idxmap = (uint8_t *)(arena + L.idx) + (size_t)wave * p.dcap;
     using A1T = typename WgAreas<K>::A1;
     using A2T = typename WgAreas<K>::A2;
     A1T &A = *reinterpret_cast<A1T *>(&s_lraw[wave][0]);
@@ -916,16 +940,16 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                 pc = kc_wave_sum_u32(pc);
                 if ((int)pc < K - 2) return;
                 if (K == 4) {
-                    wide_edges(ri, lo0, W, bm, acc);
+                    wide_edges(ri, lo0, W, bm, A.members, acc);
                     return;
                 }
                 if (pc <= 64) {
-                    const uint32_t sN = compact_local(ri, lo0, W, bm, W, idxmap, A);
+                    const uint32_t sN = compact_local(ri, lo0, W, bm, W, A);
                     local_count(A, sN, K - 2, acc);
                     return;
                 }
                 if (K >= 5 && pc <= 128) {
-                    const uint32_t sN = compact_local2(ri, lo0, W, bm, W, idxmap, A2);
+                    const uint32_t sN = compact_local2(ri, lo0, W, bm, W, A2);
                     local_count2(A2, sN, K - 2, acc);
                     return;
                 }
@@ -974,13 +998,13 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                     wave_sync();
                     if ((int)cpc < cn) continue;
                     if (cn == 2) {
-                        wide_edges(nxt, clo, W, bm, acc);
+                        wide_edges(nxt, clo, W, bm, A.members, acc);
                         wave_sync();
                     } else if (cpc <= 64) {
-                        const uint32_t sN = compact_local(nxt, clo, W, bm, W, idxmap, A);
+                        const uint32_t sN = compact_local(nxt, clo, W, bm, W, A);
                         local_count(A, sN, cn, acc);
                     } else if (K >= 5 && cpc <= 128) {
-                        const uint32_t sN = compact_local2(nxt, clo, W, bm, W, idxmap, A2);
+                        const uint32_t sN = compact_local2(nxt, clo, W, bm, W, A2);
                         local_count2(A2, sN, cn, acc);
                     } else {
                         ++depth;
@@ -1158,25 +1182,59 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
     }
     if (ev) (void)hipEventRecord(ev[1], s);
     if (q.count[1]) {
-        CountParams p = base;
-        p.queue = q.ptr[1];
-        p.count = q.count[1];
-        p.items = q.wg_items;
-        if (q.wg_items) p.count = q.wg_item_count;
-        p.next = cursors + 1;
-        p.dcap = q.max_d[1] < 65 ? 65 : q.max_d[1];
-        const WgLayout L = wg_layout(p.dcap, K);
-        const size_t per_block = L.bytes + wg_static_lds(K) + 256;
-        uint32_t per_cu = (uint32_t)(160 * 1024 / per_block);
-        if (per_cu < 1) per_cu = 1;
-        if (per_cu > 8) per_cu = 8;
-        if (tu.wg_blocks_per_cu > 0 && (uint32_t)tu.wg_blocks_per_cu < per_cu) per_cu = (uint32_t)tu.wg_blocks_per_cu;
-        uint32_t blocks = (uint32_t)di.cus * per_cu;
-        const uint32_t nitems = q.wg_items ? q.wg_item_count : q.count[1];
-        if (blocks > nitems) blocks = nitems;
+        // the attribute only caps the dynamic LDS of later launches (graph replays included)
         (void)hipFuncSetAttribute((const void *)&k_count_wg<K, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)L.bytes);
-        hipLaunchKernelGGL((k_count_wg<K, false>), dim3(blocks), dim3(WG), L.bytes, s, p);
+                                  (int)(di.lds_max - wg_static_lds(K)));
+        // resident blocks per CU for an arena sized for out-degree dmax
+        auto blocks_per_cu = [&](uint32_t dmax) {
+            const WgLayout L = wg_layout(dmax < 65 ? 65 : dmax, K);
+            const size_t per_block = L.bytes + wg_static_lds(K) + 256;
+            uint32_t per_cu = (uint32_t)(di.lds_max / per_block);
+            if (per_cu < 1) per_cu = 1;
+            if (per_cu > 8) per_cu = 8;
+            if (tu.wg_blocks_per_cu > 0 && (uint32_t)tu.wg_blocks_per_cu < per_cu)
+                per_cu = (uint32_t)tu.wg_blocks_per_cu;
+            return per_cu;
+        };
+        auto launch_wg = [&](const uint32_t *queue, uint32_t count, const uint64_t *items, uint32_t *next,
+                             uint32_t dmax) {
+            CountParams p = base;
+            p.queue = queue;
+            p.count = count;
+            p.items = items;
+            p.next = next;
+            p.dcap = dmax < 65 ? 65 : dmax;
+            const WgLayout L = wg_layout(p.dcap, K);
+            uint32_t blocks = (uint32_t)di.cus * blocks_per_cu(dmax);
+            if (blocks > count) blocks = count;
+            hipLaunchKernelGGL((k_count_wg<K, false>), dim3(blocks), dim3(WG), L.bytes, s, p);
+        };
+        if (q.wg_items) {
+            launch_wg(q.ptr[1], q.wg_item_count, q.wg_items, cursors + 1, q.max_d[1]);
+        } else if (q.wg_ncls > 1) {
+            // Consecutive out-degree classes (largest first) grouped into launches: a
+            // class joins the current group when a launch of its own would hold no
+            // more blocks per CU, or when the group is too short to keep the device
+            // busy past its tail (fewer than 4 roots per resident block).
+            uint32_t g0 = 0, cnt = q.wg_cls_cnt[0], cap = blocks_per_cu(q.wg_cls_dmax[0]);
+            for (uint32_t c = 1; c <= q.wg_ncls; ++c) {
+                if (c < q.wg_ncls) {
+                    const uint32_t pc = blocks_per_cu(q.wg_cls_dmax[c]);
+                    if (pc == cap || cnt < 4u * (uint32_t)di.cus * cap) {
+                        cnt += q.wg_cls_cnt[c];
+                        continue;
+                    }
+                }
+                launch_wg(q.ptr[1] + q.wg_cls_off[g0], cnt, nullptr, cursors + 3 + g0, q.wg_cls_dmax[g0]);
+                if (c < q.wg_ncls) {
+                    g0 = c;
+                    cnt = q.wg_cls_cnt[c];
+                    cap = blocks_per_cu(q.wg_cls_dmax[c]);
+                }
+            }
+        } else {
+            launch_wg(q.ptr[1], q.count[1], nullptr, cursors + 1, q.max_d[1]);
+        }
     }
     if (ev) (void)hipEventRecord(ev[2], s);
     if (q.count[0]) {
@@ -1228,12 +1286,13 @@ kc_status kc_count_scratch(const kc_graph *g, const kc_queue &q, int k, kc_tmp &
 
 // The counting kernels of one queue, enqueued on s with no allocation, no
 // synchronisation and no memset (so the sequence can be captured in a graph).
-// res: [0] total, [1] overflow flag, [2..4] queue cursors; gtotals/graph_of for batches.
+// res (KC_RES_WORDS words): [0] total, [1] overflow flag, then u32 queue cursors (tiers, workgroup
+// classes); gtotals/graph_of for batches.
 kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_args &a, uint64_t *res,
                           unsigned long long *gtotals, uint32_t ngraphs, const uint32_t *graph_of, uint64_t *gscratch,
                           size_t slice_words, uint32_t scratch_blocks, hipStream_t s, hipEvent_t *tier_ev) {
     const DevInfo di = dev_info(g->device);
-    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, res, (size_t)8, 0ull);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, res, (size_t)KC_RES_WORDS, 0ull);
     if (gtotals)
         hipLaunchKernelGGL(k_fill_u64, dim3((ngraphs + 255) / 256), dim3(256), 0, s, (uint64_t *)gtotals,
                            (size_t)ngraphs, 0ull);

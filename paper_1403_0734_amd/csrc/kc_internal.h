@@ -148,6 +148,8 @@ struct kc_tuning_t {
 const kc_tuning_t &kc_tuning_now();
 
 // Scheduler (kc_sched.hip)
+#define KC_WG_CLASSES 16
+#define KC_RES_WORDS 24  // per-count result block: total, overflow flag, then u32 queue cursors
 #define KC_MLP_IN 8
 #define KC_MLP_H 32
 #define KC_MLP_PARAMS (KC_MLP_IN * KC_MLP_H + KC_MLP_H + KC_MLP_H * KC_MLP_H + KC_MLP_H + KC_MLP_H + 1)
@@ -159,6 +161,10 @@ struct kc_queue {
     const uint32_t *ptr[3];    // root ranks of each tier (wave, workgroup, scratch), heaviest first
     uint32_t count[3];         // roots per tier
     uint32_t max_d[3];         // largest out-degree in each tier
+    // workgroup tier sorted by out-degree (descending): runs of one class
+    // (2^j, 2^(j+1)] of out-degrees, each launched with an arena sized for it
+    uint32_t wg_ncls = 0;
+    uint32_t wg_cls_off[KC_WG_CLASSES], wg_cls_cnt[KC_WG_CLASSES], wg_cls_dmax[KC_WG_CLASSES];
 };
 kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_max, kc_queue &q);
 kc_status kc_features(const kc_graph *g, float *d_feat, hipStream_t s);

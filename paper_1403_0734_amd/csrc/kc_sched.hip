@@ -220,6 +220,26 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
         q.count[1] = g->dq_wide - scratch;
         q.ptr[0] = g->dq + g->dq_wide;
         q.count[0] = narrow;
+        // out-degree classes of the workgroup tier, in queue order (largest first)
+        q.wg_ncls = 0;
+        uint32_t off = 0;
+        int cur = -1;
+        const uint32_t top = dmax < d_lds_max ? dmax : d_lds_max;
+        for (uint32_t d = top; d > (uint32_t)wd; --d) {
+            if (!hist[d]) continue;
+            const int c = 31 - __builtin_clz(d - 1);
+            if (c != cur) {
+                if (q.wg_ncls == KC_WG_CLASSES) break;  // cannot happen for 32-bit out-degrees
+                cur = c;
+                q.wg_cls_off[q.wg_ncls] = off;
+                q.wg_cls_cnt[q.wg_ncls] = 0;
+                q.wg_cls_dmax[q.wg_ncls] = d;
+                ++q.wg_ncls;
+            }
+            q.wg_cls_cnt[q.wg_ncls - 1] += (uint32_t)hist[d];
+            off += (uint32_t)hist[d];
+        }
+        if (off != q.count[1]) q.wg_ncls = 0;  // not a plain degree order: one launch
         return KC_OK;
     }
 
