@@ -100,7 +100,8 @@ const char *kc_status_str(kc_status s) {
 void kc_graph_destroy(kc_graph *g) {
     if (!g) return;
     kc_batch_forget(g->serial);
-    void *bufs[] = {g->rowptr, g->col, g->deg, g->ukeys, g->optr, g->ocol, g->rank2id, g->id2rank, g->mlp, g->d_res, g->dq, g->tri};
+    void *bufs[] = {g->rowptr, g->col,  g->deg, g->ukeys, g->optr,  g->ocol,  g->rank2id, g->id2rank,
+                    g->mlp,    g->d_res, g->dq,  g->tri,   g->lrows, g->wbits, g->woff};
     for (void *b : bufs)
         kc_cache_free(b, g->stream);
     (void)kc_sync(g->stream);
@@ -119,7 +120,7 @@ static kc_status create_impl(const uint32_t *src, const uint32_t *dst, uint64_t 
     g->idbits = bits_for(n);
     g->serial = g_serial.fetch_add(1);
     for (auto &e : g->ev) KC_HIP(hipEventCreate(&e));
-    KC_TRY(kc_dev_alloc((void **)&g->d_res, 64 * sizeof(uint64_t), g->stream));
+    KC_TRY(kc_dev_alloc((void **)&g->d_res, KC_RES_WORDS * sizeof(uint64_t), g->stream));
     if (!kc_pinned_scratch()) return kc_fail(KC_ENOMEM, "pinned host buffer");
     const uint32_t *ds = src, *dd = dst;
     kc_tmp cs, cd;

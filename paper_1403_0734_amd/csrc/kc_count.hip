@@ -151,8 +151,16 @@ struct CountParams {
     // batches: graph of every rank and one total per graph (null for one graph)
     const uint32_t *graph_of;
     unsigned long long *gtotals;
+    // staged G+(u) cache of the handle: wave-tier rows, larger roots' bitmaps
+    uint64_t *lrows;
+    uint64_t *wbits;
+    const uint64_t *woff;
 };
 
+
+// Queue counters of the one-wave tier: QCTR of them, QCTR_STRIDE u32 apart.
+constexpr uint32_t QCTR = 8;
+constexpr uint32_t QCTR_STRIDE = 64;
 
 // Roots per queue fetch: one device-scope atomic serves a chunk of roots.
 __device__ __forceinline__ uint32_t queue_chunk(uint32_t count, uint32_t workers, uint32_t div) {
@@ -356,6 +364,12 @@ __device__ __forceinline__ void local_count2(LocalArea2<NS> &A, uint32_t s, int 
 // are requested, or with the global colouring (which cuts Gamma+(u) first),
 // every pass holds one root.
 // ============================================================================
+// Kernel modes: stage G+(u) and count it; stage it into the handle's cache
+// only; count from the cache.
+constexpr int MODE_STAGE = 0;
+constexpr int MODE_STORE = 1;
+constexpr int MODE_CACHED = 2;
+
 // Staging state of one wave pass, overlaid on the local-graph area (whose
 // rows it shares; the rest of that area is idle until counting starts).
 struct WaveStage {
@@ -397,7 +411,7 @@ __device__ __forceinline__ void wave_stage_check(WaveSmem<K> &sm, uint32_t qh, u
     }
 }
 
-template <int K>
+template <int K, int MODE>
 __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
     __shared__ WaveSmem<K> sm_all[WAVES];
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -411,13 +425,29 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
     uint32_t my_g = 0;
     uint64_t my_base = 0;
     uint32_t cur_g = 0;               // graph whose cliques acc holds (batches)
+    // Chunk c of the queue is handed out by counter c mod QCTR (counters on
+    // separate cache lines, so that their atomics do not serialise on one
+    // address); a wave starts at its block's counter and moves on when that
+    // counter's chunks are spent.
+    const uint32_t home = blockIdx.x % QCTR;
+    uint32_t tried = 0;
 
     for (;;) {
         if (ci >= cn) {
-            uint32_t b = 0;
-            if (lane == 0) b = atomicAdd(p.next, chunk);
+            uint32_t b = 0xFFFFFFFFu;
+            if (lane == 0) {
+                while (tried < QCTR) {
+                    const uint32_t x = (home + tried) % QCTR;
+                    const uint64_t c = (uint64_t)atomicAdd(p.next + x * QCTR_STRIDE, 1u) * QCTR + x;
+                    if (c * chunk < p.count) {
+                        b = (uint32_t)(c * chunk);
+                        break;
+                    }
+                    ++tried;
+                }
+            }
             b = __shfl(b, 0, 64);
-            if (b >= p.count) break;
+            if (b == 0xFFFFFFFFu) break;
             cb = b;
             cn = (p.count - b) < chunk ? (p.count - b) : chunk;
             ci = 0;
@@ -459,110 +489,145 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
         ci += g;
         uint32_t d = S;
 
-        // Gamma+ lists into LDS; optionally cut to u's colour (global scheme, one root)
-        uint32_t a = lane < S ? p.ocol[rbase + (lane - r0)] : 0xFFFFFFFFu;
-        if (p.colored && p.scheme == KC_COLOR_GLOBAL) {
-            const uint32_t cu = node_colour(p.seed, p.rank2id[u], p.c);
-            const bool keep = lane < d && node_colour(p.seed, p.rank2id[a], p.c) == cu;
-            const uint64_t bal = __ballot(keep);
-            const uint32_t idx = (uint32_t)__popcll(bal & kc_lanemask_lt());
-            sm.nb[lane] = 0xFFFFFFFFu;
-            wave_sync();
-            if (keep) sm.nb[idx] = a;
-            wave_sync();
-            d = (uint32_t)__popcll(bal);
-            a = sm.nb[lane];
-        }
-        sm.nb[lane] = a;
-        const uint32_t lhi = lane < d ? (single ? d : r0 + rd) : 0u;
-        sm.blo[lane] = (uint8_t)(lane < d ? r0 : 0u);
-        sm.bhi[lane] = (uint8_t)lhi;
-        uint32_t len = 0;
-        uint64_t ob = 0;
-        if (lane < d) {
-            ob = p.optr[a];
-            len = (uint32_t)(p.optr[a + 1] - ob);
-        }
-        // only elements up to the largest rank of the block can match: cut each
-        // sorted out-list there (binary lifting when its last element is beyond)
-        const uint32_t bmax = __shfl(a, (lhi ? lhi - 1u : 0u) & 63u, 64);
-        if (len) {
-            const uint32_t *row = p.ocol + ob;
-            if (row[len - 1] > bmax) {
-                uint32_t b = 0;
-                for (uint32_t st = 1u << (31 - __builtin_clz(len)); st; st >>= 1)
-                    if (b + st <= len && row[b + st - 1] <= bmax) b += st;
-                len = b;
+        if (MODE == MODE_CACHED) {
+            // G+(u) rows from the staged cache, shifted into the root's block;
+            // colourings drop the edges they exclude
+            const bool mine = lane < S;
+            uint64_t row = mine ? p.lrows[rbase + (lane - r0)] << r0 : 0ull;
+            if (p.colored) {
+                const uint32_t a = mine ? p.ocol[rbase + (lane - r0)] : 0u;
+                if (p.scheme == KC_COLOR_GLOBAL) {
+                    const uint32_t cu = node_colour(p.seed, p.rank2id[u], p.c);
+                    const bool keep = mine && node_colour(p.seed, p.rank2id[a], p.c) == cu;
+                    const uint64_t kb = __ballot(keep);
+                    row = keep ? (row & kb) : 0ull;
+                } else {
+                    const uint32_t mc = mine ? root_colour(p.seed, p.rank2id[u], p.rank2id[a], p.c) : 0u;
+                    sm.colr[lane] = mc;
+                    wave_sync();
+                    uint64_t x = row, kept = 0;
+                    while (x) {
+                        const uint32_t j = (uint32_t)__builtin_ctzll(x);
+                        x &= x - 1;
+                        if (sm.colr[j] == mc) kept |= 1ull << j;
+                    }
+                    row = kept;
+                }
             }
-        }
-        const uint32_t sincl = kc_wave_incl_u32(len);
-        const uint32_t excl = sincl - len;
-        const uint32_t Ttot = __shfl(sincl, 63, 64);
-        sm.delta[lane] = ob - excl;
-        sm.A.rows[lane] = 0;
-        sm.S.filt[lane] = 0;
-        sm.S.flag[lane] = 0;
-        sm.S.flag[64 + lane] = 0;
-        const bool percol = p.colored && p.scheme == KC_COLOR_PER_ROOT;
-        if (percol) sm.colr[lane] = lane < d ? root_colour(p.seed, p.rank2id[u], p.rank2id[a], p.c) : 0u;
-        wave_sync();
-        if (lane < d) {
-            const uint32_t h = filt_hash(a);
-            atomicOr(&sm.S.filt[h >> 5], 1u << (h & 31u));
-        }
-        wave_sync();
+            sm.A.rows[lane] = row;
+        } else {
+            // Gamma+ lists into LDS; optionally cut to u's colour (global scheme, one root)
+            uint32_t a = lane < S ? p.ocol[rbase + (lane - r0)] : 0xFFFFFFFFu;
+            if (p.colored && p.scheme == KC_COLOR_GLOBAL) {
+                const uint32_t cu = node_colour(p.seed, p.rank2id[u], p.c);
+                const bool keep = lane < d && node_colour(p.seed, p.rank2id[a], p.c) == cu;
+                const uint64_t bal = __ballot(keep);
+                const uint32_t idx = (uint32_t)__popcll(bal & kc_lanemask_lt());
+                sm.nb[lane] = 0xFFFFFFFFu;
+                wave_sync();
+                if (keep) sm.nb[idx] = a;
+                wave_sync();
+                d = (uint32_t)__popcll(bal);
+                a = sm.nb[lane];
+            }
+            sm.nb[lane] = a;
+            const uint32_t lhi = lane < d ? (single ? d : r0 + rd) : 0u;
+            sm.blo[lane] = (uint8_t)(lane < d ? r0 : 0u);
+            sm.bhi[lane] = (uint8_t)lhi;
+            uint32_t len = 0;
+            uint64_t ob = 0;
+            if (lane < d) {
+                ob = p.optr[a];
+                len = (uint32_t)(p.optr[a + 1] - ob);
+            }
+            // only elements up to the largest rank of the block can match: cut each
+            // sorted out-list there (binary lifting when its last element is beyond)
+            const uint32_t bmax = __shfl(a, (lhi ? lhi - 1u : 0u) & 63u, 64);
+            if (len) {
+                const uint32_t *row = p.ocol + ob;
+                if (row[len - 1] > bmax) {
+                    uint32_t b = 0;
+                    for (uint32_t st = 1u << (31 - __builtin_clz(len)); st; st >>= 1)
+                        if (b + st <= len && row[b + st - 1] <= bmax) b += st;
+                    len = b;
+                }
+            }
+            const uint32_t sincl = kc_wave_incl_u32(len);
+            const uint32_t excl = sincl - len;
+            const uint32_t Ttot = __shfl(sincl, 63, 64);
+            sm.delta[lane] = ob - excl;
+            sm.A.rows[lane] = 0;
+            sm.S.filt[lane] = 0;
+            sm.S.flag[lane] = 0;
+            sm.S.flag[64 + lane] = 0;
+            const bool percol = p.colored && p.scheme == KC_COLOR_PER_ROOT;
+            if (percol) sm.colr[lane] = lane < d ? root_colour(p.seed, p.rank2id[u], p.rank2id[a], p.c) : 0u;
+            wave_sync();
+            if (lane < d) {
+                const uint32_t h = filt_hash(a);
+                atomicOr(&sm.S.filt[h >> 5], 1u << (h & 31u));
+            }
+            wave_sync();
 
-        // staging: row i bit j = [a_j in Gamma+(a_i)], j inside i's block.  The
-        // flattened out-lists are read 64 elements per step; the list of each
-        // element is the last one starting at or before it (window start flags
-        // and a ballot); the filter drops most non-members, the rest queue up
-        // for an exact search 64 at a time.
-        uint32_t carry = 0, qh = 0, qt = 0;
-        // two windows per step, so that each lane has two loads in flight
-        const uint64_t le_mask = kc_lanemask_lt() | (1ull << lane);
-        for (uint32_t w0 = 0; w0 < Ttot; w0 += 128) {
-            if (len && excl >= w0 && excl - w0 < 128u) sm.S.flag[excl - w0] = (uint8_t)(lane + 1u);
-            wave_sync();
-            const uint32_t f0 = sm.S.flag[lane], f1 = sm.S.flag[64 + lane];
-            const uint64_t le0 = __ballot(f0 != 0) & le_mask, le1 = __ballot(f1 != 0) & le_mask;
-            const uint32_t fo0 = __shfl(f0, le0 ? 63u - (uint32_t)__builtin_clzll(le0) : 0u, 64);
-            const uint32_t fo1 = __shfl(f1, le1 ? 63u - (uint32_t)__builtin_clzll(le1) : 0u, 64);
-            const uint32_t i0 = le0 ? fo0 - 1u : carry;
-            const uint32_t c1 = __shfl(i0, 63, 64);
-            const uint32_t i1 = le1 ? fo1 - 1u : c1;
-            carry = __shfl(i1, 63, 64);
-            if (f0) sm.S.flag[lane] = 0;
-            if (f1) sm.S.flag[64 + lane] = 0;
-            const uint32_t e0 = w0 + lane, e1 = w0 + 64u + lane;
-            uint32_t y0 = 0, y1 = 0;
-            if (e0 < Ttot) y0 = p.ocol[sm.delta[i0] + e0];
-            if (e1 < Ttot) y1 = p.ocol[sm.delta[i1] + e1];
-#pragma unroll
-            for (int hf = 0; hf < 2; ++hf) {
-                const uint32_t y = hf ? y1 : y0, i = hf ? i1 : i0;
-                bool keep = false;
-                if ((hf ? e1 : e0) < Ttot) {
-                    const uint32_t h = filt_hash(y);
-                    keep = (sm.S.filt[h >> 5] >> (h & 31u)) & 1u;
-                }
-                const uint64_t kb = __ballot(keep);
-                if (keep) {
-                    const uint32_t slot = (qt + (uint32_t)__popcll(kb & kc_lanemask_lt())) & 127u;
-                    sm.S.qy[slot] = y;
-                    sm.S.qi[slot] = (uint8_t)i;
-                }
-                qt += (uint32_t)__popcll(kb);
-                if (qt - qh >= 64u) {
-                    wave_sync();
-                    wave_stage_check(sm, qh, 64u, percol);
-                    qh += 64u;
-                    wave_sync();
+            // staging: row i bit j = [a_j in Gamma+(a_i)], j inside i's block.  The
+            // flattened out-lists are read 64 elements per step; the list of each
+            // element is the last one starting at or before it (window start flags
+            // and a ballot); the filter drops most non-members, the rest queue up
+            // for an exact search 64 at a time.
+            uint32_t carry = 0, qh = 0, qt = 0;
+            // two windows per step, so that each lane has two loads in flight
+            const uint64_t le_mask = kc_lanemask_lt() | (1ull << lane);
+            for (uint32_t w0 = 0; w0 < Ttot; w0 += 128) {
+                if (len && excl >= w0 && excl - w0 < 128u) sm.S.flag[excl - w0] = (uint8_t)(lane + 1u);
+                wave_sync();
+                const uint32_t f0 = sm.S.flag[lane], f1 = sm.S.flag[64 + lane];
+                const uint64_t le0 = __ballot(f0 != 0) & le_mask, le1 = __ballot(f1 != 0) & le_mask;
+                const uint32_t fo0 = __shfl(f0, le0 ? 63u - (uint32_t)__builtin_clzll(le0) : 0u, 64);
+                const uint32_t fo1 = __shfl(f1, le1 ? 63u - (uint32_t)__builtin_clzll(le1) : 0u, 64);
+                const uint32_t i0 = le0 ? fo0 - 1u : carry;
+                const uint32_t c1 = __shfl(i0, 63, 64);
+                const uint32_t i1 = le1 ? fo1 - 1u : c1;
+                carry = __shfl(i1, 63, 64);
+                if (f0) sm.S.flag[lane] = 0;
+                if (f1) sm.S.flag[64 + lane] = 0;
+                const uint32_t e0 = w0 + lane, e1 = w0 + 64u + lane;
+                uint32_t y0 = 0, y1 = 0;
+                if (e0 < Ttot) y0 = p.ocol[sm.delta[i0] + e0];
+                if (e1 < Ttot) y1 = p.ocol[sm.delta[i1] + e1];
+    #pragma unroll
+                for (int hf = 0; hf < 2; ++hf) {
+                    const uint32_t y = hf ? y1 : y0, i = hf ? i1 : i0;
+                    bool keep = false;
+                    if ((hf ? e1 : e0) < Ttot) {
+                        const uint32_t h = filt_hash(y);
+                        keep = (sm.S.filt[h >> 5] >> (h & 31u)) & 1u;
+                    }
+                    const uint64_t kb = __ballot(keep);
+                    if (keep) {
+                        const uint32_t slot = (qt + (uint32_t)__popcll(kb & kc_lanemask_lt())) & 127u;
+                        sm.S.qy[slot] = y;
+                        sm.S.qi[slot] = (uint8_t)i;
+                    }
+                    qt += (uint32_t)__popcll(kb);
+                    if (qt - qh >= 64u) {
+                        wave_sync();
+                        wave_stage_check(sm, qh, 64u, percol);
+                        qh += 64u;
+                        wave_sync();
+                    }
                 }
             }
+            if (qt != qh) {
+                wave_sync();
+                wave_stage_check(sm, qh, qt - qh, percol);
+            }
         }
-        if (qt != qh) {
+        if (MODE == MODE_STORE) {
+            // keep the staged rows (root-local bit positions) for later counts
             wave_sync();
-            wave_stage_check(sm, qh, qt - qh, percol);
+            if (lane < d) p.lrows[rbase + (lane - r0)] = sm.A.rows[lane] >> r0;
+            wave_sync();
+            continue;
         }
         wave_sync();
         local_count(sm.A, d, K - 1, acc);
@@ -784,7 +849,7 @@ __device__ __forceinline__ void wide_edges(const uint64_t *C, uint32_t lo, uint3
     if (cnt) flush(cnt);
 }
 
-template <int K, bool GLOBAL>
+template <int K, bool GLOBAL, int MODE>
 __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
     extern __shared__ __align__(16) unsigned char smem_dyn[];
     __shared__ __align__(16) uint64_t s_lraw[WAVES][wg_local_bytes<K>() / 8];
@@ -839,87 +904,148 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
         const uint64_t base = p.optr[u];
         uint32_t d = (uint32_t)(p.optr[u + 1] - base);
 
-        for (uint32_t t = tid; t < d; t += WG) nb[t] = p.ocol[base + t];
-        __syncthreads();
-        if (p.colored && p.scheme == KC_COLOR_GLOBAL) {
-            // keep only the nodes of u's colour, preserving order
-            const uint32_t cu = node_colour(p.seed, p.rank2id[u], p.c);
-            for (uint32_t t = tid; t < d; t += WG) seg[t] = node_colour(p.seed, p.rank2id[nb[t]], p.c) == cu ? 1u : 0u;
-            __syncthreads();
-            if (tid == 0) {
-                uint32_t w = 0;
-                for (uint32_t t = 0; t < d; ++t)
-                    if (seg[t]) nb[w++] = nb[t];
-                s_misc[1] = w;
-            }
-            __syncthreads();
-            d = s_misc[1];
-        }
-        const uint32_t W = (d + 63) / 64;
-        // out-degrees of Gamma+(u) and their exclusive prefix
-        for (uint32_t t = tid; t < d; t += WG) {
-            const uint32_t x = nb[t];
-            seg[t] = (uint32_t)(p.optr[x + 1] - p.optr[x]);
-            if (p.colored && p.scheme == KC_COLOR_PER_ROOT) colr[t] = root_colour(p.seed, p.rank2id[u], p.rank2id[x], p.c);
-        }
-        __syncthreads();
-        if (tid < 64) {
-            uint32_t carry = 0;
-            for (uint32_t c0 = 0; c0 < d; c0 += 64) {
-                const uint32_t t = c0 + lane;
-                const uint32_t v = t < d ? seg[t] : 0u;
-                const uint32_t inc = kc_wave_incl_u32(v);
-                if (t < d) {
-                    seg[t] = carry + inc - v;
-                    delta[t] = p.optr[nb[t]] - (carry + inc - v);
+        uint32_t W;
+        uint64_t words;
+        if (MODE == MODE_CACHED) {
+            // G+(u) from the staged cache; colourings drop the edges they exclude
+            W = (d + 63) / 64;
+            words = tri_words(d);
+            const uint64_t *src = p.wbits + p.woff[u];
+            for (uint64_t w = tid; w < words; w += WG) bm[w] = src[w];
+            if (p.colored) {
+                for (uint32_t t = tid; t < d; t += WG) nb[t] = p.ocol[base + t];
+                __syncthreads();
+                if (p.scheme == KC_COLOR_GLOBAL) {
+                    // nodes of u's colour; rows of the others and edges to them vanish
+                    const uint32_t cu = node_colour(p.seed, p.rank2id[u], p.c);
+                    for (uint32_t t = tid; t < d; t += WG)
+                        colr[t] = node_colour(p.seed, p.rank2id[nb[t]], p.c) == cu ? 1u : 0u;
+                    __syncthreads();
+                    for (uint32_t l = tid; l < W; l += WG) {  // keep mask, word l, as two halves in seg
+                        uint64_t km = 0;
+                        for (uint32_t b = 0; b < 64 && 64 * l + b < d; ++b)
+                            if (colr[64 * l + b]) km |= 1ull << b;
+                        seg[2 * l] = (uint32_t)km;
+                        seg[2 * l + 1] = (uint32_t)(km >> 32);
+                    }
+                    __syncthreads();
+                    for (uint32_t i = tid; i < d; i += WG) {
+                        uint64_t *ri = bm + tri_rowoff(i, W) - ((i + 1) >> 6);
+                        const bool ki = colr[i] != 0u;
+                        for (uint32_t l = (i + 1) >> 6; l < W; ++l)
+                            ri[l] = ki ? ri[l] & ((uint64_t)seg[2 * l] | ((uint64_t)seg[2 * l + 1] << 32)) : 0ull;
+                    }
+                } else {
+                    // edges whose two ends differ in colour vanish
+                    for (uint32_t t = tid; t < d; t += WG)
+                        colr[t] = root_colour(p.seed, p.rank2id[u], p.rank2id[nb[t]], p.c);
+                    __syncthreads();
+                    for (uint32_t i = tid; i < d; i += WG) {
+                        uint64_t *ri = bm + tri_rowoff(i, W) - ((i + 1) >> 6);
+                        const uint32_t ci0 = colr[i];
+                        for (uint32_t l = (i + 1) >> 6; l < W; ++l) {
+                            uint64_t x = ri[l], kept = 0;
+                            while (x) {
+                                const uint32_t b = (uint32_t)__builtin_ctzll(x);
+                                x &= x - 1;
+                                if (colr[64 * l + b] == ci0) kept |= 1ull << b;
+                            }
+                            ri[l] = kept;
+                        }
+                    }
                 }
-                carry += __shfl(inc, 63, 64);
             }
-            if (lane == 0) seg[d] = carry;
-        }
-        const uint64_t words = tri_words(d);
-        for (uint64_t w = tid; w < words; w += WG) bm[w] = 0;
-        for (uint32_t h = tid; h < hsize / 2; h += WG) reinterpret_cast<uint32_t *>(htab)[h] = HEMPTY;
-        if (tid == 0) s_misc[3] = 0;
-        __syncthreads();
-        for (uint32_t t = tid; t < d; t += WG) hash_insert(htab, hbits, nb[t], t);
-        __syncthreads();
-        const uint32_t Ttot = seg[d];
-        if (d > 0) {
-            const uint32_t alast = nb[d - 1];
-            if (Ttot >= 32u * d) {
-                // long out-lists: one wave per list, coalesced reads, stop past alast
-                for (;;) {
-                    uint32_t i = 0;
-                    if (lane == 0) i = atomicAdd(&s_misc[3], 1u);
-                    i = __shfl(i, 0, 64);
-                    if (i >= d) break;
-                    const uint64_t b = delta[i] + seg[i];
-                    const uint32_t len = seg[i + 1] - seg[i];
-                    uint64_t *ri = bm + tri_rowoff(i, W) - ((i + 1) >> 6);
-                    for (uint32_t o = 0; o < len; o += 64) {
-                        const uint32_t t = o + lane;
-                        const uint32_t y = t < len ? p.ocol[b + t] : 0xFFFFFFFFu;
-                        const bool in = y <= alast;
-                        if (!__any(in)) break;  // the list is sorted
-                        if (!in) continue;
+        } else {
+            for (uint32_t t = tid; t < d; t += WG) nb[t] = p.ocol[base + t];
+            __syncthreads();
+            if (p.colored && p.scheme == KC_COLOR_GLOBAL) {
+                // keep only the nodes of u's colour, preserving order
+                const uint32_t cu = node_colour(p.seed, p.rank2id[u], p.c);
+                for (uint32_t t = tid; t < d; t += WG) seg[t] = node_colour(p.seed, p.rank2id[nb[t]], p.c) == cu ? 1u : 0u;
+                __syncthreads();
+                if (tid == 0) {
+                    uint32_t w = 0;
+                    for (uint32_t t = 0; t < d; ++t)
+                        if (seg[t]) nb[w++] = nb[t];
+                    s_misc[1] = w;
+                }
+                __syncthreads();
+                d = s_misc[1];
+            }
+            W = (d + 63) / 64;
+            // out-degrees of Gamma+(u) and their exclusive prefix
+            for (uint32_t t = tid; t < d; t += WG) {
+                const uint32_t x = nb[t];
+                seg[t] = (uint32_t)(p.optr[x + 1] - p.optr[x]);
+                if (p.colored && p.scheme == KC_COLOR_PER_ROOT) colr[t] = root_colour(p.seed, p.rank2id[u], p.rank2id[x], p.c);
+            }
+            __syncthreads();
+            if (tid < 64) {
+                uint32_t carry = 0;
+                for (uint32_t c0 = 0; c0 < d; c0 += 64) {
+                    const uint32_t t = c0 + lane;
+                    const uint32_t v = t < d ? seg[t] : 0u;
+                    const uint32_t inc = kc_wave_incl_u32(v);
+                    if (t < d) {
+                        seg[t] = carry + inc - v;
+                        delta[t] = p.optr[nb[t]] - (carry + inc - v);
+                    }
+                    carry += __shfl(inc, 63, 64);
+                }
+                if (lane == 0) seg[d] = carry;
+            }
+            words = tri_words(d);
+            for (uint64_t w = tid; w < words; w += WG) bm[w] = 0;
+            for (uint32_t h = tid; h < hsize / 2; h += WG) reinterpret_cast<uint32_t *>(htab)[h] = HEMPTY;
+            if (tid == 0) s_misc[3] = 0;
+            __syncthreads();
+            for (uint32_t t = tid; t < d; t += WG) hash_insert(htab, hbits, nb[t], t);
+            __syncthreads();
+            const uint32_t Ttot = seg[d];
+            if (d > 0) {
+                const uint32_t alast = nb[d - 1];
+                if (Ttot >= 32u * d) {
+                    // long out-lists: one wave per list, coalesced reads, stop past alast
+                    for (;;) {
+                        uint32_t i = 0;
+                        if (lane == 0) i = atomicAdd(&s_misc[3], 1u);
+                        i = __shfl(i, 0, 64);
+                        if (i >= d) break;
+                        const uint64_t b = delta[i] + seg[i];
+                        const uint32_t len = seg[i + 1] - seg[i];
+                        uint64_t *ri = bm + tri_rowoff(i, W) - ((i + 1) >> 6);
+                        for (uint32_t o = 0; o < len; o += 64) {
+                            const uint32_t t = o + lane;
+                            const uint32_t y = t < len ? p.ocol[b + t] : 0xFFFFFFFFu;
+                            const bool in = y <= alast;
+                            if (!__any(in)) break;  // the list is sorted
+                            if (!in) continue;
+                            const uint32_t j = hash_find(htab, hbits, nb, y);
+                            if (j == HEMPTY) continue;
+                            if (p.colored && p.scheme == KC_COLOR_PER_ROOT && colr[i] != colr[j]) continue;
+                            atomicOr((unsigned long long *)(ri + (j >> 6)), 1ull << (j & 63));
+                        }
+                    }
+                } else {
+                    for (uint32_t e = tid; e < Ttot; e += WG) {
+                        const uint32_t i = seg_find(seg, d, e);
+                        const uint32_t y = p.ocol[delta[i] + e];
+                        if (y > alast) continue;
                         const uint32_t j = hash_find(htab, hbits, nb, y);
                         if (j == HEMPTY) continue;
                         if (p.colored && p.scheme == KC_COLOR_PER_ROOT && colr[i] != colr[j]) continue;
-                        atomicOr((unsigned long long *)(ri + (j >> 6)), 1ull << (j & 63));
+                        atomicOr((unsigned long long *)(bm_row(bm, i, W) + (j >> 6)), 1ull << (j & 63));
                     }
                 }
-            } else {
-                for (uint32_t e = tid; e < Ttot; e += WG) {
-                    const uint32_t i = seg_find(seg, d, e);
-                    const uint32_t y = p.ocol[delta[i] + e];
-                    if (y > alast) continue;
-                    const uint32_t j = hash_find(htab, hbits, nb, y);
-                    if (j == HEMPTY) continue;
-                    if (p.colored && p.scheme == KC_COLOR_PER_ROOT && colr[i] != colr[j]) continue;
-                    atomicOr((unsigned long long *)(bm_row(bm, i, W) + (j >> 6)), 1ull << (j & 63));
-                }
             }
+        }
+        if (MODE == MODE_STORE) {
+            // keep the staged bitmap for later counts
+            __syncthreads();
+            uint64_t *dst = p.wbits + p.woff[u];
+            for (uint64_t w = tid; w < words; w += WG) dst[w] = bm[w];
+            __syncthreads();
+            continue;
         }
         if (tid == 0) s_misc[2] = 0;
         __syncthreads();
@@ -1164,7 +1290,7 @@ DevInfo dev_info(int device) {
     return di;
 }
 
-template <int K>
+template <int K, int MODE>
 void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors, const DevInfo &di, hipStream_t s,
                   uint64_t *gscratch, size_t slice_words, uint32_t scratch_blocks, hipEvent_t *ev) {
     const kc_tuning_t &tu = kc_tuning_now();
@@ -1178,12 +1304,12 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
         p.gscratch = gscratch;
         p.slice_words = slice_words;
         p.dcap = q.max_d[2];
-        hipLaunchKernelGGL((k_count_wg<K, true>), dim3(scratch_blocks), dim3(WG), 0, s, p);
+        hipLaunchKernelGGL((k_count_wg<K, true, MODE>), dim3(scratch_blocks), dim3(WG), 0, s, p);
     }
     if (ev) (void)hipEventRecord(ev[1], s);
     if (q.count[1]) {
         // the attribute only caps the dynamic LDS of later launches (graph replays included)
-        (void)hipFuncSetAttribute((const void *)&k_count_wg<K, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute((const void *)&k_count_wg<K, false, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)(di.lds_max - wg_static_lds(K)));
         // resident blocks per CU for an arena sized for out-degree dmax
         auto blocks_per_cu = [&](uint32_t dmax) {
@@ -1207,7 +1333,7 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
             const WgLayout L = wg_layout(p.dcap, K);
             uint32_t blocks = (uint32_t)di.cus * blocks_per_cu(dmax);
             if (blocks > count) blocks = count;
-            hipLaunchKernelGGL((k_count_wg<K, false>), dim3(blocks), dim3(WG), L.bytes, s, p);
+            hipLaunchKernelGGL((k_count_wg<K, false, MODE>), dim3(blocks), dim3(WG), L.bytes, s, p);
         };
         if (q.wg_items) {
             launch_wg(q.ptr[1], q.wg_item_count, q.wg_items, cursors + 1, q.max_d[1]);
@@ -1245,7 +1371,7 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
         uint32_t blocks = (q.count[0] + WAVES - 1) / WAVES;
         const uint32_t cap = (uint32_t)di.cus * (uint32_t)(tu.wave_blocks_per_cu > 0 ? tu.wave_blocks_per_cu : 8);
         if (blocks > cap) blocks = cap;
-        hipLaunchKernelGGL((k_count_wave<K>), dim3(blocks), dim3(WG), 0, s, p);
+        hipLaunchKernelGGL((k_count_wave<K, MODE>), dim3(blocks), dim3(WG), 0, s, p);
     }
     if (ev) (void)hipEventRecord(ev[3], s);
 }
@@ -1255,7 +1381,68 @@ __global__ void k_fill_u64(uint64_t *p, size_t n, uint64_t v) {
     if (i < n) p[i] = v;
 }
 
+// cache words of each root: its packed bitmap when it is above the wave tier
+__global__ void k_stage_sizes(const uint64_t *optr, uint32_t n, uint32_t wd, uint64_t *words) {
+    const size_t x = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const uint64_t d = optr[x + 1] - optr[x];
+    words[x] = d > wd ? tri_words(d) : 0ull;
+}
+
 }  // namespace
+
+// Stage every root's G+(u) into the handle's cache (wave tier split at wd).
+// Leaves the handle uncached (staged = -1) when the cache would take more than
+// half of the free device memory.
+kc_status kc_stage(kc_graph *g, int wd) {
+    if (g->staged != 0 && g->stage_wd == wd) return KC_OK;
+    hipStream_t s = g->stream;
+    kc_cache_free(g->lrows, s);
+    kc_cache_free(g->wbits, s);
+    kc_cache_free(g->woff, s);
+    g->lrows = g->wbits = g->woff = nullptr;
+    g->staged = 0;
+    const uint32_t n = g->n;
+    uint64_t *woff = nullptr;
+    KC_TRY(kc_dev_alloc((void **)&woff, ((size_t)n + 1) * 8, s));
+    {
+        kc_tmp sizes;
+        KC_TRY(kc_tmp_alloc(sizes, (size_t)(n ? n : 1) * 8, s));
+        hipLaunchKernelGGL(k_stage_sizes, dim3((n + 255) / 256), dim3(256), 0, s, (const uint64_t *)g->optr, n,
+                           (uint32_t)wd, sizes.as<uint64_t>());
+        KC_HIP(hipGetLastError());
+        KC_TRY(kc_scan_excl_u64(sizes.as<uint64_t>(), woff, n, woff + n, s));
+    }
+    uint64_t *h = kc_pinned_scratch();
+    KC_HIP(hipMemcpyAsync(h, woff + n, 8, hipMemcpyDeviceToHost, s));
+    KC_TRY(kc_sync(s));
+    const uint64_t total = h[0];
+    size_t fr = 0, tot = 0;
+    KC_HIP(hipMemGetInfo(&fr, &tot));
+    if ((g->m + total) * 8 > fr / 2) {
+        kc_cache_free(woff, s);
+        g->staged = -1;
+        g->stage_wd = wd;
+        return KC_OK;
+    }
+    g->woff = woff;
+    KC_TRY(kc_dev_alloc((void **)&g->lrows, (size_t)(g->m ? g->m : 1) * 8, s));
+    KC_TRY(kc_dev_alloc((void **)&g->wbits, (size_t)(total ? total : 1) * 8, s));
+    kc_queue q;
+    KC_TRY(kc_build_queue(g, 3, KC_SCHED_DEGREE, kc_lds_dcap(g->device, 3), q));
+    kc_tmp gscr;
+    size_t slice_words = 0;
+    uint32_t scratch_blocks = 0;
+    KC_TRY(kc_count_scratch(g, q, 3, gscr, slice_words, scratch_blocks));
+    kc_count_args a;
+    a.k = 3;
+    a.store = 1;
+    KC_TRY(kc_count_launch(g, q, a, g->d_res, nullptr, 0, nullptr, gscr.as<uint64_t>(), slice_words, scratch_blocks,
+                           s, nullptr));
+    g->staged = 1;
+    g->stage_wd = wd;
+    return KC_OK;
+}
 
 // Largest out-degree whose workgroup layout (packed bitmap included) fits in LDS.
 uint32_t kc_lds_dcap(int device, int k) {
@@ -1286,13 +1473,14 @@ kc_status kc_count_scratch(const kc_graph *g, const kc_queue &q, int k, kc_tmp &
 
 // The counting kernels of one queue, enqueued on s with no allocation, no
 // synchronisation and no memset (so the sequence can be captured in a graph).
-// res (KC_RES_WORDS words): [0] total, [1] overflow flag, then u32 queue cursors (tiers, workgroup
-// classes); gtotals/graph_of for batches.
+// res (KC_RES_WORDS words): [0] total, [1] overflow flag, then u32 queue cursors: the wave
+// tier's counters at 0, QCTR_STRIDE, ...; workgroup at 1, scratch at 2, workgroup classes at
+// 3 + c; gtotals/graph_of for batches.
 kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_args &a, uint64_t *res,
                           unsigned long long *gtotals, uint32_t ngraphs, const uint32_t *graph_of, uint64_t *gscratch,
                           size_t slice_words, uint32_t scratch_blocks, hipStream_t s, hipEvent_t *tier_ev) {
     const DevInfo di = dev_info(g->device);
-    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, res, (size_t)KC_RES_WORDS, 0ull);
+    hipLaunchKernelGGL(k_fill_u64, dim3((KC_RES_WORDS + 63) / 64), dim3(64), 0, s, res, (size_t)KC_RES_WORDS, 0ull);
     if (gtotals)
         hipLaunchKernelGGL(k_fill_u64, dim3((ngraphs + 255) / 256), dim3(256), 0, s, (uint64_t *)gtotals,
                            (size_t)ngraphs, 0ull);
@@ -1313,11 +1501,23 @@ kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_a
     p.chunk_div = (uint32_t)(kc_tuning_now().chunk_div > 0 ? kc_tuning_now().chunk_div : 8);
     p.graph_of = graph_of;
     p.gtotals = gtotals;
+    p.lrows = g->lrows;
+    p.wbits = g->wbits;
+    p.woff = g->woff;
     uint32_t *cursors = (uint32_t *)(res + 2);
+    if (a.store) {
+        // staging into the cache does not depend on k
+        launch_tiers<3, MODE_STORE>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev);
+        KC_HIP(hipGetLastError());
+        return KC_OK;
+    }
     switch (a.k) {
-#define KC_CASE(KK)                                                                             \
-    case KK:                                                                                    \
-        launch_tiers<KK>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev); \
+#define KC_CASE(KK)                                                                                          \
+    case KK:                                                                                                 \
+        if (a.cached)                                                                                        \
+            launch_tiers<KK, MODE_CACHED>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev); \
+        else                                                                                                 \
+            launch_tiers<KK, MODE_STAGE>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev);  \
         break;
         KC_CASE(3)
         KC_CASE(4)
@@ -1344,12 +1544,23 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
     KC_TRY(kc_build_queue(g, a.k, a.policy, dcap, q));
     KC_HIP(hipEventRecord(g->ev[1], s));
     if (a.per_root) KC_HIP(hipMemsetAsync(a.per_root, 0, (size_t)g->n * sizeof(uint64_t), s));
+    // the first count on a handle stages every G+(u) once; later counts read it
+    // (KC_STAGE_CACHE=0 stages per call instead)
+    kc_count_args ac = a;
+    const char *sc = getenv("KC_STAGE_CACHE");
+    if (!(sc && sc[0] == '0')) {
+        int wd = kc_tuning_now().wave_dmax;
+        wd = wd < 1 ? 1 : (wd > 64 ? 64 : wd);
+        kc_graph *gm = const_cast<kc_graph *>(g);
+        KC_TRY(kc_stage(gm, wd));
+        ac.cached = gm->staged == 1;
+    }
     kc_tmp gscr;
     size_t slice_words = 0;
     uint32_t scratch_blocks = 0;
     KC_TRY(kc_count_scratch(g, q, a.k, gscr, slice_words, scratch_blocks));
     hipEvent_t tev[4] = {g->ev[2], g->ev[3], g->ev[4], g->ev[5]};
-    KC_TRY(kc_count_launch(g, q, a, g->d_res, nullptr, 0, nullptr, gscr.as<uint64_t>(), slice_words, scratch_blocks,
+    KC_TRY(kc_count_launch(g, q, ac, g->d_res, nullptr, 0, nullptr, gscr.as<uint64_t>(), slice_words, scratch_blocks,
                            s, tev));
     uint64_t *h_res = kc_pinned_scratch();
     KC_HIP(hipMemcpyAsync(h_res, g->d_res, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));

@@ -95,6 +95,14 @@ struct kc_graph {
     uint32_t dq_wide = 0, dq_narrow = 0;
     uint64_t *dq_hist = nullptr;  // host, max_outdeg + 1 entries
 
+    // Staged local graphs G+(u), built by the first count and read by later ones:
+    // roots with out-degree <= stage_wd keep one 64-bit row per node of
+    // Gamma+(u) at lrows[optr[u] + i] (bit j: a_j in Gamma+(a_i)); larger roots
+    // keep their packed upper-triangular bitmap at wbits + woff[u].
+    int staged = 0;  // 1 built, -1 not kept (memory), 0 not yet
+    int stage_wd = 0;
+    uint64_t *lrows = nullptr, *wbits = nullptr, *woff = nullptr;
+
     uint64_t serial = 0;  // unique per handle (batch plans are keyed by it)
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     float t_schedule = 0.f, t_count = 0.f, t_total = 0.f;
@@ -122,6 +130,8 @@ struct kc_count_args {
     int scheme = KC_COLOR_PER_ROOT;
     uint64_t *per_root = nullptr;  // device [n] by original id, optional
     int policy = KC_SCHED_DEGREE;
+    int cached = 0;  // count from the handle's staged G+(u) cache
+    int store = 0;   // stage G+(u) into the cache, count nothing
 };
 kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *total, int *overflow);
 struct kc_queue;
@@ -149,7 +159,7 @@ const kc_tuning_t &kc_tuning_now();
 
 // Scheduler (kc_sched.hip)
 #define KC_WG_CLASSES 16
-#define KC_RES_WORDS 24  // per-count result block: total, overflow flag, then u32 queue cursors
+#define KC_RES_WORDS 512  // per-count result block: total, overflow flag, then u32 queue cursors
 #define KC_MLP_IN 8
 #define KC_MLP_H 32
 #define KC_MLP_PARAMS (KC_MLP_IN * KC_MLP_H + KC_MLP_H + KC_MLP_H * KC_MLP_H + KC_MLP_H + KC_MLP_H + 1)

@@ -151,6 +151,27 @@ def test_colour_raw_counts_match_oracle(scheme):
         _close(h)
 
 
+@pytest.mark.parametrize("cache", ["1", "0"])
+def test_staged_cache_and_per_call_staging(monkeypatch, cache):
+    """Counts from the handle's staged G+(u) cache (the default) and with staging on
+    every call: exact totals, per-root counts and both colourings, every tier."""
+    monkeypatch.setenv("KC_STAGE_CACHE", cache)
+    for el in [SMALL[2], SMALL[11], SMALL[12], MULTI_TILE[0]]:
+        og = O.OracleGraph.from_edgelist(el)
+        h = device_graph(el)
+        ks = bounded_ks(og, 3, 7, budget=5e6)
+        for k in ks:
+            announce(f"stage cache={cache} {el.name} k={k}")
+            assert K.kc_count(h, k) == og.count(k), (el.name, k)
+        for scheme in (K.KC_COLOR_PER_ROOT, K.KC_COLOR_GLOBAL):
+            for k in ks[:3]:
+                e = K.kc_count_colored(h, k, 3, 77, scheme)
+                assert e.raw == og.count_colored(k, 3, 77, scheme), (el.name, k, scheme)
+        c, _ = per_root(h, el.n, ks[-1])
+        assert np.array_equal(c, og.count_per_root(ks[-1]))
+        _close(h)
+
+
 def test_repeat_runs_identical():
     el = SMALL[12]
     h = device_graph(el)
