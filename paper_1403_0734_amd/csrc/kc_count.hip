@@ -880,14 +880,28 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
     uint32_t cur_g = 0;
     int ovf = 0;
     uint32_t cb = 0, cn = 0, ci = 0;
+    const uint32_t home = blockIdx.x % QCTR;  // the queue's counters, as in the one-wave tier
+    uint32_t tried = 0;
 
     for (;;) {
         if (ci >= cn) {
-            if (tid == 0) s_misc[0] = atomicAdd(p.next, chunk);
+            if (tid == 0) {
+                uint32_t b = 0xFFFFFFFFu;
+                while (tried < QCTR) {
+                    const uint32_t x = (home + tried) % QCTR;
+                    const uint64_t c = (uint64_t)atomicAdd(p.next + x * QCTR_STRIDE, 1u) * QCTR + x;
+                    if (c * chunk < p.count) {
+                        b = (uint32_t)(c * chunk);
+                        break;
+                    }
+                    ++tried;
+                }
+                s_misc[0] = b;
+            }
             __syncthreads();
             cb = s_misc[0];
             __syncthreads();
-            if (cb >= p.count) break;
+            if (cb == 0xFFFFFFFFu) break;
             cn = (p.count - cb) < chunk ? (p.count - cb) : chunk;
             ci = 0;
         }
@@ -1473,9 +1487,9 @@ kc_status kc_count_scratch(const kc_graph *g, const kc_queue &q, int k, kc_tmp &
 
 // The counting kernels of one queue, enqueued on s with no allocation, no
 // synchronisation and no memset (so the sequence can be captured in a graph).
-// res (KC_RES_WORDS words): [0] total, [1] overflow flag, then u32 queue cursors: the wave
-// tier's counters at 0, QCTR_STRIDE, ...; workgroup at 1, scratch at 2, workgroup classes at
-// 3 + c; gtotals/graph_of for batches.
+// res (KC_RES_WORDS words): [0] total, [1] overflow flag, then u32 queue counters, each
+// queue's QCTR of them QCTR_STRIDE apart from its first: wave tier at 0, workgroup at 1,
+// scratch at 2, workgroup classes at 3 + c; gtotals/graph_of for batches.
 kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_args &a, uint64_t *res,
                           unsigned long long *gtotals, uint32_t ngraphs, const uint32_t *graph_of, uint64_t *gscratch,
                           size_t slice_words, uint32_t scratch_blocks, hipStream_t s, hipEvent_t *tier_ev) {
