@@ -187,16 +187,39 @@ __device__ __forceinline__ void add_to(const CountParams &p, uint32_t gid, uint6
 // Rows of lanes >= s must be zero.
 // ============================================================================
 // NS = depth-first stack entries: counting ell-cliques uses ell - 3 of them.
+// Depth-first stack levels kept in registers; deeper stacks live in LDS (where
+// registers would spill).  The one-wave kernel keeps two levels, the
+// workgroup kernel two as well (three spill).
+constexpr int LC_LDS_FROM = 2;  // local areas hold LDS stacks for more levels than this
+constexpr int LC_REG_WAVE = 2;
+constexpr int LC_REG_WG = 2;
+
 template <int NS>
 struct LocalArea {
     uint64_t rows[64];
     uint32_t epre[64];
     uint32_t members[64];
-    uint64_t stk[NS][64];
+    uint64_t stk[NS > LC_LDS_FROM ? NS : 1][64];  // depth-first stacks when too deep for registers
 };
 
-template <int NS>
+// Per-lane depth-first stacks of at most N levels live in registers: an entry
+// is read or written through a chain of selects on the depth.
+template <int N>
+__device__ __forceinline__ uint64_t st_get(const uint64_t (&st)[N], int d) {
+    uint64_t v = st[0];
+#pragma unroll
+    for (int i = 1; i < N; ++i) v = d == i ? st[i] : v;
+    return v;
+}
+template <int N>
+__device__ __forceinline__ void st_set(uint64_t (&st)[N], int d, uint64_t v) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) st[i] = d == i ? v : st[i];
+}
+
+template <int REGL, int NS>
 __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int ell, uint64_t &acc) {
+    static_assert(REGL >= LC_LDS_FROM, "levels neither in registers nor in LDS");
     const uint32_t lane = kc_lane();
     const uint64_t row = A.rows[lane];
     if (ell <= 1) {
@@ -216,6 +239,18 @@ __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int el
     // Idle lanes are refilled together, once at least REFILL of them wait (or
     // no lane is busy): task t of the i-th idle lane is next + i.
     constexpr uint32_t REFILL = 16;
+    constexpr bool REG = NS <= REGL;
+    uint64_t st[REG ? NS : 1];
+#pragma unroll
+    for (int l = 0; l < (REG ? NS : 1); ++l) st[l] = 0;
+    auto sget = [&](int dd) -> uint64_t {
+        if constexpr (REG) return st_get(st, dd);
+        else return A.stk[dd][lane];
+    };
+    auto sset = [&](int dd, uint64_t v) {
+        if constexpr (REG) st_set(st, dd, v);
+        else A.stk[dd][lane] = v;
+    };
     int depth = -1;
     uint32_t next = 0;
     for (;;) {
@@ -233,27 +268,27 @@ __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int el
                     acc += (uint64_t)__popcll(P);
                 } else if ((int)__popcll(P) >= R) {
                     depth = 0;
-                    A.stk[0][lane] = P;
+                    sset(0, P);
                 }
             }
         } else if (nidle == 64) {
             break;
         }
         if (depth >= 0) {
-            uint64_t cur = A.stk[depth][lane];
+            uint64_t cur = sget(depth);
             if (cur == 0) {
                 --depth;
             } else {
                 const uint32_t v = (uint32_t)__builtin_ctzll(cur);
                 cur &= cur - 1;
-                A.stk[depth][lane] = cur;
+                sset(depth, cur);
                 const uint64_t child = cur & A.rows[v];
                 const int rem = R - depth - 1;  // nodes still to choose after v
                 if (rem == 1) {
                     acc += (uint64_t)__popcll(child);
                 } else if ((int)__popcll(child) >= rem) {
                     ++depth;
-                    A.stk[depth][lane] = child;
+                    sset(depth, child);
                 }
             }
         }
@@ -271,7 +306,7 @@ struct LocalArea2 {
     uint64_t rows[128][2];
     uint32_t epre[128];
     uint32_t members[128];
-    uint64_t stk[NS][2][64];
+    uint64_t stk[NS > LC_LDS_FROM ? NS : 1][2][64];
 };
 
 __device__ __forceinline__ uint32_t select_bit2(uint64_t w0, uint64_t w1, uint32_t r) {
@@ -300,6 +335,28 @@ __device__ __forceinline__ void local_count2(LocalArea2<NS> &A, uint32_t s, int 
     A.epre[2 * lane + 1] = incl - cb;
     wave_sync();
     constexpr uint32_t REFILL = 16;
+    constexpr bool REG = NS <= LC_LDS_FROM;
+    uint64_t st0[REG ? NS : 1], st1[REG ? NS : 1];
+#pragma unroll
+    for (int l = 0; l < (REG ? NS : 1); ++l) st0[l] = st1[l] = 0;
+    auto sget = [&](int dd, uint64_t &a0, uint64_t &a1) {
+        if constexpr (REG) {
+            a0 = st_get(st0, dd);
+            a1 = st_get(st1, dd);
+        } else {
+            a0 = A.stk[dd][0][lane];
+            a1 = A.stk[dd][1][lane];
+        }
+    };
+    auto sset = [&](int dd, uint64_t v0, uint64_t v1) {
+        if constexpr (REG) {
+            st_set(st0, dd, v0);
+            st_set(st1, dd, v1);
+        } else {
+            A.stk[dd][0][lane] = v0;
+            A.stk[dd][1][lane] = v1;
+        }
+    };
     int depth = -1;
     uint32_t next = 0;
     for (;;) {
@@ -318,15 +375,15 @@ __device__ __forceinline__ void local_count2(LocalArea2<NS> &A, uint32_t s, int 
                     acc += (uint64_t)pc;
                 } else if (pc >= R) {
                     depth = 0;
-                    A.stk[0][0][lane] = p0;
-                    A.stk[0][1][lane] = p1;
+                    sset(0, p0, p1);
                 }
             }
         } else if (nidle == 64) {
             break;
         }
         if (depth >= 0) {
-            uint64_t c0 = A.stk[depth][0][lane], c1 = A.stk[depth][1][lane];
+            uint64_t c0, c1;
+            sget(depth, c0, c1);
             if ((c0 | c1) == 0) {
                 --depth;
             } else {
@@ -338,8 +395,7 @@ __device__ __forceinline__ void local_count2(LocalArea2<NS> &A, uint32_t s, int 
                     v = 64u + (uint32_t)__builtin_ctzll(c1);
                     c1 &= c1 - 1;
                 }
-                A.stk[depth][0][lane] = c0;
-                A.stk[depth][1][lane] = c1;
+                sset(depth, c0, c1);
                 const uint64_t h0 = c0 & A.rows[v][0], h1 = c1 & A.rows[v][1];
                 const int pc = __popcll(h0) + __popcll(h1);
                 const int rem = R - depth - 1;
@@ -347,8 +403,7 @@ __device__ __forceinline__ void local_count2(LocalArea2<NS> &A, uint32_t s, int 
                     acc += (uint64_t)pc;
                 } else if (pc >= rem) {
                     ++depth;
-                    A.stk[depth][0][lane] = h0;
-                    A.stk[depth][1][lane] = h1;
+                    sset(depth, h0, h1);
                 }
             }
         }
@@ -379,7 +434,8 @@ struct WaveStage {
     uint8_t qi[128];    // ... and the list (local node) it came from
     uint8_t flag[128];  // per 128-element step: 1 + list starting at each slot
 };
-static_assert(sizeof(WaveStage) <= sizeof(LocalArea<1>), "staging overlay must fit the local-graph area");
+static_assert(offsetof(WaveStage, rows) == 0 && offsetof(LocalArea<1>, rows) == 0,
+              "staging rows must alias the local graph's rows");
 
 template <int K>
 struct WaveSmem {
@@ -630,7 +686,7 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
             continue;
         }
         wave_sync();
-        local_count(sm.A, d, K - 1, acc);
+        local_count<LC_REG_WAVE>(sm.A, d, K - 1, acc);
 
         if (p.per_root) {
             const uint64_t q = kc_wave_sum_checked(acc, &ovf);
@@ -1085,7 +1141,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                 }
                 if (pc <= 64) {
                     const uint32_t sN = compact_local(ri, lo0, W, bm, W, A);
-                    local_count(A, sN, K - 2, acc);
+                    local_count<LC_REG_WG>(A, sN, K - 2, acc);
                     return;
                 }
                 if (K >= 5 && pc <= 128) {
@@ -1142,7 +1198,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                         wave_sync();
                     } else if (cpc <= 64) {
                         const uint32_t sN = compact_local(nxt, clo, W, bm, W, A);
-                        local_count(A, sN, cn, acc);
+                        local_count<LC_REG_WG>(A, sN, cn, acc);
                     } else if (K >= 5 && cpc <= 128) {
                         const uint32_t sN = compact_local2(nxt, clo, W, bm, W, A2);
                         local_count2(A2, sN, cn, acc);
@@ -1232,7 +1288,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                         }
                         A.rows[lane] = lrow;
                         wave_sync();
-                        local_count(A, S, K - 2, acc);
+                        local_count<LC_REG_WG>(A, S, K - 2, acc);
                         cm &= ~fit;
                     }
                 }
