@@ -193,13 +193,19 @@ __device__ __forceinline__ void add_to(const CountParams &p, uint32_t gid, uint6
 constexpr int LC_LDS_FROM = 2;  // local areas hold LDS stacks for more levels than this
 constexpr int LC_REG_WAVE = 2;
 constexpr int LC_REG_WG = 2;
+// Edges of a local graph listed in LDS (i << 8 | j) when there are at most this many;
+// a task is then one read instead of a segment search and a bit selection.
+constexpr uint32_t LC_ELIST = 512;
 
 template <int NS>
 struct LocalArea {
     uint64_t rows[64];
     uint32_t epre[64];
-    uint32_t members[64];
-    uint64_t stk[NS > LC_LDS_FROM ? NS : 1][64];  // depth-first stacks when too deep for registers
+    union {
+        uint32_t members[64];       // compaction (before counting)
+        uint16_t elist[LC_ELIST];   // counting
+    };
+    uint64_t stk[NS > LC_LDS_FROM ? NS : 0][64];  // depth-first stacks when too deep for registers
 };
 
 // Per-lane depth-first stacks of at most N levels live in registers: an entry
@@ -234,8 +240,27 @@ __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int el
     const uint32_t ce = (uint32_t)__popcll(row);
     const uint32_t ei = kc_wave_incl_u32(ce);
     const uint32_t E = __shfl(ei, 63, 64);
-    A.epre[lane] = ei - ce;
+    const bool listed = E <= LC_ELIST;
+    if (listed) {
+        uint64_t r = row;
+        uint32_t pos = ei - ce;
+        while (r) {
+            A.elist[pos++] = (uint16_t)((lane << 8) | (uint32_t)__builtin_ctzll(r));
+            r &= r - 1;
+        }
+    } else {
+        A.epre[lane] = ei - ce;
+    }
     wave_sync();
+    if (R == 1 && listed) {
+        // one level: every edge task is a single intersection
+        for (uint32_t t = lane; t < E; t += 64) {
+            const uint32_t e = A.elist[t];
+            acc += (uint64_t)__popcll(A.rows[e >> 8] & A.rows[e & 255u]);
+        }
+        wave_sync();
+        return;
+    }
     // Idle lanes are refilled together, once at least REFILL of them wait (or
     // no lane is busy): task t of the i-th idle lane is next + i.
     constexpr uint32_t REFILL = 16;
@@ -260,10 +285,15 @@ __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int el
             const uint32_t t = next + (uint32_t)__popcll(idle & kc_lanemask_lt());
             next += nidle;
             if (depth < 0 && t < E) {
-                const uint32_t i = seg_find(A.epre, s, t);
-                const uint64_t ri = A.rows[i];
-                const uint32_t j = select_bit(ri, t - A.epre[i]);
-                const uint64_t P = ri & A.rows[j];
+                uint64_t P;
+                if (listed) {
+                    const uint32_t e = A.elist[t];
+                    P = A.rows[e >> 8] & A.rows[e & 255u];
+                } else {
+                    const uint32_t i = seg_find(A.epre, s, t);
+                    const uint64_t ri = A.rows[i];
+                    P = ri & A.rows[select_bit(ri, t - A.epre[i])];
+                }
                 if (R == 1) {
                     acc += (uint64_t)__popcll(P);
                 } else if ((int)__popcll(P) >= R) {
