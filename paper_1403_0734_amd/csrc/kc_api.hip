@@ -250,6 +250,7 @@ kc_status kc_get_csr(const kc_graph *g, uint64_t *row_ptr, uint32_t *col, uint32
     g_msg[0] = 0;
     if (!g) return kc_fail(KC_EINVAL, "graph is NULL");
     hipStream_t s = g->stream;
+    if (row_ptr || col) KC_TRY(kc_build_csr(const_cast<kc_graph *>(g)));
     if (row_ptr) KC_HIP(hipMemcpyAsync(row_ptr, g->rowptr, ((size_t)g->n + 1) * 8, hipMemcpyDeviceToDevice, s));
     if (col && g->m) KC_HIP(hipMemcpyAsync(col, g->col, 2 * (size_t)g->m * 4, hipMemcpyDeviceToDevice, s));
     if (deg) KC_HIP(hipMemcpyAsync(deg, g->deg, (size_t)g->n * 4, hipMemcpyDeviceToDevice, s));

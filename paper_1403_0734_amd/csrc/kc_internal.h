@@ -63,11 +63,11 @@ struct kc_graph {
     uint64_t m = 0;       // undirected edges of the simple graph
     int idbits = 1;       // bits that hold any id in [0, n)
 
-    // simple graph (symmetric CSR) and degrees
+    // simple graph: degrees, unique edges, symmetric CSR (built on request)
     uint64_t *rowptr = nullptr;  // n + 1
     uint32_t *col = nullptr;     // 2m
     uint32_t *deg = nullptr;     // n
-    uint64_t *ukeys = nullptr;   // 2m sorted (row << idbits | col) keys, held from ingest to orientation
+    uint64_t *ukeys = nullptr;   // m sorted unique edges (min << idbits | max)
 
     // orientation, rank space
     int oriented = 0;
@@ -120,6 +120,7 @@ kc_status kc_radix_sort_u64(uint64_t *keys, uint64_t *tmp, size_t n, int bit_lo,
 // Ingest and orientation (kc_graph.hip)
 kc_status kc_canonicalise(kc_graph *g, const uint32_t *d_src, const uint32_t *d_dst);
 kc_status kc_orient_impl(kc_graph *g);
+kc_status kc_build_csr(kc_graph *g);
 
 // Counting (kc_count.hip)
 struct kc_count_args {
