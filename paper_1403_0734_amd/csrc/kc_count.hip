@@ -158,9 +158,42 @@ struct CountParams {
 };
 
 
-// Queue counters of the one-wave tier: QCTR of them, QCTR_STRIDE u32 apart.
-constexpr uint32_t QCTR = 8;
+// Queue counters: chunk c of a queue is handed out by counter c mod QCTR, the
+// counters QCTR_STRIDE u32 (256 bytes) apart so that their atomics do not
+// serialise on one address; beside each (QCTR_FLAG u32 further, on another cache
+// line) a flag is set once the counter is spent.
+constexpr uint32_t QCTR = 32;
 constexpr uint32_t QCTR_STRIDE = 64;
+constexpr uint32_t QCTR_FLAG = 32;
+
+// Next chunk start of a queue for the calling wave (all 64 lanes call it), or
+// 0xFFFFFFFF once every counter is spent.  The wave starts at its home counter;
+// `dead` holds the counters it has seen spent.  Each pass either returns or adds
+// a counter to `dead`, so it ends within QCTR passes.  A stale flag costs one
+// atomic, never a wrong chunk.
+__device__ __forceinline__ uint32_t next_chunk(uint32_t *ctr, uint32_t count, uint32_t chunk, uint32_t home,
+                                               uint32_t &dead) {
+    const uint32_t lane = kc_lane();
+    uint32_t x = home;
+    for (;;) {
+        if (!((dead >> x) & 1u)) {
+            uint32_t b = 0xFFFFFFFFu;
+            if (lane == 0) {
+                const uint64_t c = (uint64_t)atomicAdd(ctr + x * QCTR_STRIDE, 1u) * QCTR + x;
+                if (c * chunk < count) b = (uint32_t)(c * chunk);
+                else ctr[x * QCTR_STRIDE + QCTR_FLAG] = 1u;
+            }
+            b = __shfl(b, 0, 64);
+            if (b != 0xFFFFFFFFu) return b;
+            dead |= 1u << x;
+        }
+        const bool live = lane < QCTR && !((dead >> lane) & 1u) && ctr[lane * QCTR_STRIDE + QCTR_FLAG] == 0u;
+        const uint64_t lm = __ballot(live);
+        if (!lm) return 0xFFFFFFFFu;
+        const uint64_t after = lm & ~((2ull << x) - 1ull);  // live counters past x
+        x = (uint32_t)__builtin_ctzll(after ? after : lm);
+    }
+}
 
 // Roots per queue fetch: one device-scope atomic serves a chunk of roots.
 __device__ __forceinline__ uint32_t queue_chunk(uint32_t count, uint32_t workers, uint32_t div) {
@@ -511,28 +544,12 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
     uint32_t my_g = 0;
     uint64_t my_base = 0;
     uint32_t cur_g = 0;               // graph whose cliques acc holds (batches)
-    // Chunk c of the queue is handed out by counter c mod QCTR (counters on
-    // separate cache lines, so that their atomics do not serialise on one
-    // address); a wave starts at its block's counter and moves on when that
-    // counter's chunks are spent.
-    const uint32_t home = blockIdx.x % QCTR;
-    uint32_t tried = 0;
+    const uint32_t home = (blockIdx.x * WAVES + wave) % QCTR;
+    uint32_t dead = 0;
 
     for (;;) {
         if (ci >= cn) {
-            uint32_t b = 0xFFFFFFFFu;
-            if (lane == 0) {
-                while (tried < QCTR) {
-                    const uint32_t x = (home + tried) % QCTR;
-                    const uint64_t c = (uint64_t)atomicAdd(p.next + x * QCTR_STRIDE, 1u) * QCTR + x;
-                    if (c * chunk < p.count) {
-                        b = (uint32_t)(c * chunk);
-                        break;
-                    }
-                    ++tried;
-                }
-            }
-            b = __shfl(b, 0, 64);
+            const uint32_t b = next_chunk(p.next, p.count, chunk, home, dead);
             if (b == 0xFFFFFFFFu) break;
             cb = b;
             cn = (p.count - b) < chunk ? (p.count - b) : chunk;
@@ -967,22 +984,13 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
     int ovf = 0;
     uint32_t cb = 0, cn = 0, ci = 0;
     const uint32_t home = blockIdx.x % QCTR;  // the queue's counters, as in the one-wave tier
-    uint32_t tried = 0;
+    uint32_t dead = 0;
 
     for (;;) {
         if (ci >= cn) {
-            if (tid == 0) {
-                uint32_t b = 0xFFFFFFFFu;
-                while (tried < QCTR) {
-                    const uint32_t x = (home + tried) % QCTR;
-                    const uint64_t c = (uint64_t)atomicAdd(p.next + x * QCTR_STRIDE, 1u) * QCTR + x;
-                    if (c * chunk < p.count) {
-                        b = (uint32_t)(c * chunk);
-                        break;
-                    }
-                    ++tried;
-                }
-                s_misc[0] = b;
+            if (wave == 0) {
+                const uint32_t b = next_chunk(p.next, p.count, chunk, home, dead);
+                if (lane == 0) s_misc[0] = b;
             }
             __syncthreads();
             cb = s_misc[0];
@@ -1574,8 +1582,9 @@ kc_status kc_count_scratch(const kc_graph *g, const kc_queue &q, int k, kc_tmp &
 // The counting kernels of one queue, enqueued on s with no allocation, no
 // synchronisation and no memset (so the sequence can be captured in a graph).
 // res (KC_RES_WORDS words): [0] total, [1] overflow flag, then u32 queue counters, each
-// queue's QCTR of them QCTR_STRIDE apart from its first: wave tier at 0, workgroup at 1,
-// scratch at 2, workgroup classes at 3 + c; gtotals/graph_of for batches.
+// queue's QCTR of them QCTR_STRIDE apart from its first (spent flags QCTR_FLAG further):
+// wave tier at 0, workgroup at 1, scratch at 2, workgroup classes at 3 + c; gtotals/graph_of
+// for batches.
 kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_args &a, uint64_t *res,
                           unsigned long long *gtotals, uint32_t ngraphs, const uint32_t *graph_of, uint64_t *gscratch,
                           size_t slice_words, uint32_t scratch_blocks, hipStream_t s, hipEvent_t *tier_ev) {

@@ -160,7 +160,7 @@ const kc_tuning_t &kc_tuning_now();
 
 // Scheduler (kc_sched.hip)
 #define KC_WG_CLASSES 16
-#define KC_RES_WORDS 512  // per-count result block: total, overflow flag, then u32 queue cursors
+#define KC_RES_WORDS 1040  // per-count result block: total, overflow flag, then u32 queue counters
 #define KC_MLP_IN 8
 #define KC_MLP_H 32
 #define KC_MLP_PARAMS (KC_MLP_IN * KC_MLP_H + KC_MLP_H + KC_MLP_H * KC_MLP_H + KC_MLP_H + KC_MLP_H + 1)
