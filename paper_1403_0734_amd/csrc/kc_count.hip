@@ -488,6 +488,9 @@ constexpr int MODE_STAGE = 0;
 constexpr int MODE_STORE = 1;
 constexpr int MODE_CACHED = 2;
 
+// 64-element windows of flattened out-lists read per staging step
+constexpr uint32_t STAGE_WINDOWS = 4;
+
 // Staging state of one wave pass, overlaid on the local-graph area (whose
 // rows it shares; the rest of that area is idle until counting starts).
 struct WaveStage {
@@ -495,7 +498,7 @@ struct WaveStage {
     uint32_t filt[64];  // 2048-bit membership filter of the packed Gamma+ lists
     uint32_t qy[128];   // ring of filter survivors: out-list element ...
     uint8_t qi[128];    // ... and the list (local node) it came from
-    uint8_t flag[128];  // per 128-element step: 1 + list starting at each slot
+    uint8_t flag[64 * STAGE_WINDOWS];  // per step: 1 + the list starting at each slot
 };
 static_assert(offsetof(WaveStage, rows) == 0 && offsetof(LocalArea<1>, rows) == 0,
               "staging rows must alias the local graph's rows");
@@ -643,16 +646,23 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
                 ob = p.optr[a];
                 len = (uint32_t)(p.optr[a + 1] - ob);
             }
-            // only elements up to the largest rank of the block can match: cut each
-            // sorted out-list there (binary lifting when its last element is beyond)
+            // only elements from the next member a_{i+1} of the block up to its largest
+            // rank can match: cut each sorted out-list to that range (two binary
+            // liftings side by side, when an end is beyond); the block's last node
+            // has no later member
             const uint32_t bmax = __shfl(a, (lhi ? lhi - 1u : 0u) & 63u, 64);
+            const uint32_t bnext = __shfl(a, (lane + 1u) & 63u, 64);
+            if (lane + 1u >= lhi) len = 0;
             if (len) {
                 const uint32_t *row = p.ocol + ob;
-                if (row[len - 1] > bmax) {
-                    uint32_t b = 0;
-                    for (uint32_t st = 1u << (31 - __builtin_clz(len)); st; st >>= 1)
-                        if (b + st <= len && row[b + st - 1] <= bmax) b += st;
-                    len = b;
+                if (row[len - 1] > bmax || row[0] < bnext) {
+                    uint32_t bh = 0, bl = 0;  // elements <= bmax, elements < bnext
+                    for (uint32_t st = 1u << (31 - __builtin_clz(len)); st; st >>= 1) {
+                        if (bh + st <= len && row[bh + st - 1] <= bmax) bh += st;
+                        if (bl + st <= len && row[bl + st - 1] < bnext) bl += st;
+                    }
+                    ob += bl;
+                    len = bh > bl ? bh - bl : 0u;
                 }
             }
             const uint32_t sincl = kc_wave_incl_u32(len);
@@ -661,8 +671,8 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
             sm.delta[lane] = ob - excl;
             sm.A.rows[lane] = 0;
             sm.S.filt[lane] = 0;
-            sm.S.flag[lane] = 0;
-            sm.S.flag[64 + lane] = 0;
+#pragma unroll
+            for (uint32_t h = 0; h < STAGE_WINDOWS; ++h) sm.S.flag[64 * h + lane] = 0;
             const bool percol = p.colored && p.scheme == KC_COLOR_PER_ROOT;
             if (percol) sm.colr[lane] = lane < d ? root_colour(p.seed, p.rank2id[u], p.rank2id[a], p.c) : 0u;
             wave_sync();
@@ -678,38 +688,39 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
             // and a ballot); the filter drops most non-members, the rest queue up
             // for an exact search 64 at a time.
             uint32_t carry = 0, qh = 0, qt = 0;
-            // two windows per step, so that each lane has two loads in flight
+            // STAGE_WINDOWS windows per step, so that each lane has that many loads in flight
             const uint64_t le_mask = kc_lanemask_lt() | (1ull << lane);
-            for (uint32_t w0 = 0; w0 < Ttot; w0 += 128) {
-                if (len && excl >= w0 && excl - w0 < 128u) sm.S.flag[excl - w0] = (uint8_t)(lane + 1u);
+            for (uint32_t w0 = 0; w0 < Ttot; w0 += 64u * STAGE_WINDOWS) {
+                if (len && excl >= w0 && excl - w0 < 64u * STAGE_WINDOWS) sm.S.flag[excl - w0] = (uint8_t)(lane + 1u);
                 wave_sync();
-                const uint32_t f0 = sm.S.flag[lane], f1 = sm.S.flag[64 + lane];
-                const uint64_t le0 = __ballot(f0 != 0) & le_mask, le1 = __ballot(f1 != 0) & le_mask;
-                const uint32_t fo0 = __shfl(f0, le0 ? 63u - (uint32_t)__builtin_clzll(le0) : 0u, 64);
-                const uint32_t fo1 = __shfl(f1, le1 ? 63u - (uint32_t)__builtin_clzll(le1) : 0u, 64);
-                const uint32_t i0 = le0 ? fo0 - 1u : carry;
-                const uint32_t c1 = __shfl(i0, 63, 64);
-                const uint32_t i1 = le1 ? fo1 - 1u : c1;
-                carry = __shfl(i1, 63, 64);
-                if (f0) sm.S.flag[lane] = 0;
-                if (f1) sm.S.flag[64 + lane] = 0;
-                const uint32_t e0 = w0 + lane, e1 = w0 + 64u + lane;
-                uint32_t y0 = 0, y1 = 0;
-                if (e0 < Ttot) y0 = p.ocol[sm.delta[i0] + e0];
-                if (e1 < Ttot) y1 = p.ocol[sm.delta[i1] + e1];
-    #pragma unroll
-                for (int hf = 0; hf < 2; ++hf) {
-                    const uint32_t y = hf ? y1 : y0, i = hf ? i1 : i0;
+                uint32_t iw[STAGE_WINDOWS], yw[STAGE_WINDOWS];
+#pragma unroll
+                for (uint32_t h = 0; h < STAGE_WINDOWS; ++h) {
+                    const uint32_t f = sm.S.flag[64 * h + lane];
+                    const uint64_t le = __ballot(f != 0) & le_mask;
+                    const uint32_t fo = __shfl(f, le ? 63u - (uint32_t)__builtin_clzll(le) : 0u, 64);
+                    iw[h] = le ? fo - 1u : carry;
+                    carry = __shfl(iw[h], 63, 64);
+                    if (f) sm.S.flag[64 * h + lane] = 0;
+                }
+#pragma unroll
+                for (uint32_t h = 0; h < STAGE_WINDOWS; ++h) {
+                    const uint32_t e = w0 + 64u * h + lane;
+                    yw[h] = e < Ttot ? p.ocol[sm.delta[iw[h]] + e] : 0u;
+                }
+#pragma unroll
+                for (uint32_t h = 0; h < STAGE_WINDOWS; ++h) {
+                    const uint32_t y = yw[h];
                     bool keep = false;
-                    if ((hf ? e1 : e0) < Ttot) {
-                        const uint32_t h = filt_hash(y);
-                        keep = (sm.S.filt[h >> 5] >> (h & 31u)) & 1u;
+                    if (w0 + 64u * h + lane < Ttot) {
+                        const uint32_t hs = filt_hash(y);
+                        keep = (sm.S.filt[hs >> 5] >> (hs & 31u)) & 1u;
                     }
                     const uint64_t kb = __ballot(keep);
                     if (keep) {
                         const uint32_t slot = (qt + (uint32_t)__popcll(kb & kc_lanemask_lt())) & 127u;
                         sm.S.qy[slot] = y;
-                        sm.S.qi[slot] = (uint8_t)i;
+                        sm.S.qi[slot] = (uint8_t)iw[h];
                     }
                     qt += (uint32_t)__popcll(kb);
                     if (qt - qh >= 64u) {
