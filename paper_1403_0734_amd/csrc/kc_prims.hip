@@ -93,8 +93,10 @@ kc_status scan_excl(const T *in, T *out, size_t n, T *d_total, hipStream_t s) {
 }
 
 // ----------------------------------------------------------------------------
-// Radix sort: 8-bit digits, 256 threads x 16 keys per tile.  Per pass:
-// tile histograms (digit-major), one exclusive scan, stable scatter.
+// Radix sort: 8-bit digits, 256 threads x 16 keys per tile.  Per pass, three
+// launches: tile histograms (digit-major), an exclusive scan of each digit's
+// row of tile counts (one block per digit, which also writes the digit's
+// total), and a stable scatter that scans the 256 digit totals itself.
 constexpr int RS_THREADS = 256;
 constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
@@ -128,29 +130,63 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const uint64_t *keys, si
     hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = s_h[threadIdx.x];
 }
 
+// offs[d * nblocks + b] = exclusive scan of hist[d * nblocks + 0 .. nblocks), for the
+// digit d of this block; total[d] = the digit's count.
+__global__ void __launch_bounds__(RS_THREADS) k_rs_rowscan(const uint32_t *hist, uint32_t *offs, uint32_t nblocks,
+                                                           uint32_t *total) {
+    __shared__ uint32_t s_wt[RS_THREADS / 64];
+    const uint32_t *row = hist + (size_t)blockIdx.x * nblocks;
+    uint32_t *orow = offs + (size_t)blockIdx.x * nblocks;
+    const uint32_t tid = threadIdx.x, wave = tid >> 6;
+    const uint32_t per = (nblocks + RS_THREADS - 1) / RS_THREADS;
+    const uint32_t b0 = tid * per, b1 = b0 + per < nblocks ? b0 + per : nblocks;
+    uint32_t sum = 0;
+    for (uint32_t b = b0; b < b1; ++b) sum += row[b];
+    const uint32_t inc = kc_wave_incl_u32(sum);
+    if ((tid & 63) == 63) s_wt[wave] = inc;
+    __syncthreads();
+    uint32_t run = inc - sum;
+    for (uint32_t w = 0; w < wave; ++w) run += s_wt[w];
+    for (uint32_t b = b0; b < b1; ++b) {
+        orow[b] = run;
+        run += row[b];
+    }
+    if (tid == RS_THREADS - 1) total[blockIdx.x] = run;
+}
+
 // Stable scatter of one tile: keys are first ranked and placed in LDS in digit
 // order (tile-local start of each digit from this tile's histogram), then
 // written out in that order, so that each digit's keys of the tile leave as
 // one contiguous run.
 __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint64_t *in, uint64_t *out, size_t n, int shift,
                                                            const uint32_t *hist, const uint32_t *offs,
-                                                           uint32_t nblocks) {
+                                                           const uint32_t *dtotal, uint32_t nblocks) {
     __shared__ uint64_t s_keys[RS_TILE];
     __shared__ uint32_t s_start[256];  // tile-local first position of each digit
     __shared__ uint32_t s_run[256];    // keys of each digit placed so far
     __shared__ uint32_t s_gbase[256];  // global first position of each digit's run
     __shared__ uint32_t s_w[RS_THREADS / 64][256];
     __shared__ uint32_t s_wt[RS_THREADS / 64];
+    __shared__ uint32_t s_dt[RS_THREADS / 64];
     const int tid = threadIdx.x, wave = tid >> 6;
+    // tile-local digit starts from this tile's counts; global digit starts from the totals
     const uint32_t c = hist[(size_t)tid * nblocks + blockIdx.x];
     const uint32_t inc = kc_wave_incl_u32(c);
-    if ((tid & 63) == 63) s_wt[wave] = inc;
-    s_gbase[tid] = offs[(size_t)tid * nblocks + blockIdx.x];
+    const uint32_t dt = dtotal[tid];
+    const uint32_t dinc = kc_wave_incl_u32(dt);
+    if ((tid & 63) == 63) {
+        s_wt[wave] = inc;
+        s_dt[wave] = dinc;
+    }
     s_run[tid] = 0;
     __syncthreads();
-    uint32_t before = 0;
-    for (int w = 0; w < wave; ++w) before += s_wt[w];
+    uint32_t before = 0, dbefore = 0;
+    for (int w = 0; w < wave; ++w) {
+        before += s_wt[w];
+        dbefore += s_dt[w];
+    }
     s_start[tid] = before + inc - c;
+    s_gbase[tid] = dbefore + dinc - dt + offs[(size_t)tid * nblocks + blockIdx.x];
     const size_t base = (size_t)blockIdx.x * RS_TILE;
     for (int r = 0; r < RS_ITEMS; ++r) {
         const size_t i = base + (size_t)r * RS_THREADS + tid;
@@ -198,19 +234,22 @@ kc_status kc_radix_sort_u64(uint64_t *keys, uint64_t *tmp, size_t n, int bit_lo,
     if (n <= 1 || bit_hi <= bit_lo) return KC_OK;
     if (n >= (1ull << 32)) return kc_fail(KC_EINVAL, "radix sort of %zu keys exceeds 2^32", n);
     const uint32_t nblocks = (uint32_t)((n + RS_TILE - 1) / RS_TILE);
-    kc_tmp hist, offs;
+    kc_tmp hist, offs, dtot;
     KC_TRY(kc_tmp_alloc(hist, (size_t)256 * nblocks * sizeof(uint32_t), s));
     KC_TRY(kc_tmp_alloc(offs, (size_t)256 * nblocks * sizeof(uint32_t), s));
+    KC_TRY(kc_tmp_alloc(dtot, 256 * sizeof(uint32_t), s));
     uint64_t *src = keys, *dst = tmp;
     int passes = 0;
     for (int shift = bit_lo; shift < bit_hi; shift += 8, ++passes) {
         hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(RS_THREADS), 0, s, (const uint64_t *)src, n, shift,
                            hist.as<uint32_t>(), nblocks);
         KC_HIP(hipGetLastError());
-        KC_TRY(kc_scan_excl_u32(hist.as<uint32_t>(), offs.as<uint32_t>(), (size_t)256 * nblocks, nullptr, s));
+        hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(RS_THREADS), 0, s, (const uint32_t *)hist.as<uint32_t>(),
+                           offs.as<uint32_t>(), nblocks, dtot.as<uint32_t>());
+        KC_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(RS_THREADS), 0, s, (const uint64_t *)src, dst, n,
                            shift, (const uint32_t *)hist.as<uint32_t>(), (const uint32_t *)offs.as<uint32_t>(),
-                           nblocks);
+                           (const uint32_t *)dtot.as<uint32_t>(), nblocks);
         KC_HIP(hipGetLastError());
         uint64_t *t = src;
         src = dst;

@@ -22,16 +22,16 @@ inline unsigned grid_for(size_t n) { return (unsigned)((n + T - 1) / T); }
 constexpr uint32_t HIST_LDS = 1024;  // out-degrees below this are binned in LDS first
 
 // key = part (wide/narrow) | 24-bit out-degree complement | rank
-__global__ void k_degree_keys(const uint64_t *optr, uint32_t n, uint32_t wd, uint64_t *keys, uint32_t *flag,
-                              uint32_t *hist) {
+__global__ void k_degree_keys(const uint64_t *optr, uint32_t n, uint32_t wd, uint32_t dmax, int db,
+                              uint64_t *keys, uint32_t *flag, uint32_t *hist) {
     __shared__ uint32_t s_h[HIST_LDS];
     for (uint32_t i = threadIdx.x; i < HIST_LDS; i += blockDim.x) s_h[i] = 0;
     __syncthreads();
     const size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u < n) {
+        // sort key above the rank: wave-tier bit, then dmax - d (larger out-degree first)
         const uint32_t d = (uint32_t)(optr[u + 1] - optr[u]);
-        const uint32_t dc = d < 0xFFFFFFu ? d : 0xFFFFFFu;
-        keys[u] = ((uint64_t)(d <= wd ? 1u : 0u) << 62) | ((uint64_t)(0xFFFFFFu - dc) << 32) | (uint64_t)u;
+        keys[u] = ((uint64_t)(d <= wd ? 1u : 0u) << (32 + db)) | ((uint64_t)(dmax - d) << 32) | (uint64_t)u;
         flag[u] = d >= 2 ? 1u : 0u;
         if (d < HIST_LDS) atomicAdd(&s_h[d], 1u);
         else atomicAdd(&hist[d], 1u);
@@ -143,8 +143,10 @@ kc_status build_degree_cache(kc_graph *g, uint32_t wd) {
     KC_TRY(kc_tmp_alloc(hist, (size_t)hcap * 4, s));
     KC_TRY(kc_tmp_alloc(total, 8, s));
     KC_HIP(hipMemsetAsync(hist.p, 0, (size_t)hcap * 4, s));
+    int db = 1;  // bits of dmax - d
+    while (db < 31 && ((uint64_t)1 << db) <= (uint64_t)g->max_outdeg) ++db;
     hipLaunchKernelGGL(k_degree_keys, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)g->optr, n, wd,
-                       keys.as<uint64_t>(), flag.as<uint32_t>(), hist.as<uint32_t>());
+                       g->max_outdeg, db, keys.as<uint64_t>(), flag.as<uint32_t>(), hist.as<uint32_t>());
     KC_HIP(hipGetLastError());
     KC_TRY(kc_scan_excl_u32(flag.as<uint32_t>(), pos.as<uint32_t>(), n, total.as<uint32_t>(), s));
     uint32_t *h = (uint32_t *)kc_pinned_buffer(((size_t)hn + 1) * 4);
@@ -170,7 +172,7 @@ kc_status build_degree_cache(kc_graph *g, uint32_t wd) {
                            (const uint32_t *)flag.as<uint32_t>(), (const uint32_t *)pos.as<uint32_t>(), n,
                            keys2.as<uint64_t>());
         KC_HIP(hipGetLastError());
-        KC_TRY(kc_radix_sort_u64(keys2.as<uint64_t>(), tmp.as<uint64_t>(), active, 32, 64, s));
+        KC_TRY(kc_radix_sort_u64(keys2.as<uint64_t>(), tmp.as<uint64_t>(), active, 32, 33 + db, s));
         hipLaunchKernelGGL(k_queue_from_keys, dim3(grid_for(active)), dim3(T), 0, s,
                            (const uint64_t *)keys2.as<uint64_t>(), active, g->dq);
         KC_HIP(hipGetLastError());
