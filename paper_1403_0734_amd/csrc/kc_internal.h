@@ -82,6 +82,7 @@ struct kc_graph {
     float *mlp = nullptr;   // device weights (KC_MLP_PARAMS floats + normalisation)
     int mlp_loaded = 0;
     uint64_t *tri = nullptr;  // per-root edges of G+(u) by original id (scheduler feature), cached
+    float *feat = nullptr;    // scheduler features that do not depend on k, cached (rank order)
 
     // small result area on the device: [0] total, [1] overflow flag, [2..] cursors
     uint64_t *d_res = nullptr;

@@ -32,6 +32,18 @@ constexpr int NORM = 2 * NF + 2;  // feature means, stds, label mean, std
 constexpr int T = 256;
 inline unsigned grid_for(size_t n) { return (unsigned)((n + T - 1) / T); }
 
+// log of the expected (k-1)-cliques of G+(u) for an Erdos-Renyi graph of its size
+// and edge density: log C(d, k-1) + C(k-1, 2) log(density), clamped to [-10, 60]
+__device__ __forceinline__ double log_cliques(uint32_t d, double dens, int k) {
+    double lc = -10.0;
+    if (d >= (uint32_t)(k - 1) && dens > 0) {
+        const double r = k - 1;
+        lc = lgamma((double)d + 1.0) - lgamma(r + 1.0) - lgamma((double)d - r + 1.0) + 0.5 * r * (r - 1.0) * log(dens);
+        lc = lc < -10.0 ? -10.0 : (lc > 60.0 ? 60.0 : lc);
+    }
+    return lc;
+}
+
 __global__ void k_features(const uint64_t *optr, const uint32_t *ocol, const uint32_t *rank2id, const uint32_t *deg,
                            const uint64_t *tri_by_id, uint32_t n, int k, float *feat) {
     const size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -50,12 +62,7 @@ __global__ void k_features(const uint64_t *optr, const uint32_t *ocol, const uin
     const double ep = (double)tri_by_id[id];
     const double pairs = d >= 2 ? 0.5 * (double)d * (double)(d - 1) : 0.0;
     const double dens = pairs > 0 ? ep / pairs : 0.0;
-    double lc = -10.0;
-    if (d >= (uint32_t)(k - 1) && dens > 0) {
-        const double r = k - 1;
-        lc = lgamma((double)d + 1.0) - lgamma(r + 1.0) - lgamma((double)d - r + 1.0) + 0.5 * r * (r - 1.0) * log(dens);
-        lc = lc < -10.0 ? -10.0 : (lc > 60.0 ? 60.0 : lc);
-    }
+    const double lc = log_cliques(d, dens, k);
     float *f = feat + u * NF;
     f[0] = (float)log1p((double)d);
     f[1] = (float)log1p(wedges);
@@ -91,16 +98,23 @@ __device__ __forceinline__ float mlp_forward(const float *P, const float *x, flo
 }
 
 // inference: pred[u] = predicted log1p(work) of root u (raw features, normalised here)
-__global__ void __launch_bounds__(T) k_mlp_infer(const float *feat, uint32_t n, const float *params, float *pred) {
+// Inference from features cached without k: the two k-dependent ones (k / 10 and
+// the log expected cliques) are computed here.
+__global__ void __launch_bounds__(T) k_mlp_infer_k(const float *feat, uint32_t n, int k, const uint64_t *optr,
+                                                   const float *params, float *pred) {
     __shared__ float P[NP + NORM];
     for (int i = threadIdx.x; i < NP + NORM; i += blockDim.x) P[i] = params[i];
     __syncthreads();
     const size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n) return;
     const float *norm = P + NP;
-    float x[NF], h1[H], z1[H], h2[H], z2[H];
+    float f[NF], x[NF], h1[H], z1[H], h2[H], z2[H];
 #pragma unroll
-    for (int i = 0; i < NF; ++i) x[i] = (feat[u * NF + i] - norm[i]) / norm[NF + i];
+    for (int i = 0; i < NF; ++i) f[i] = feat[u * NF + i];
+    f[6] = (float)k / 10.0f;
+    f[7] = (float)log_cliques((uint32_t)(optr[u + 1] - optr[u]), (double)f[5], k);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) x[i] = (f[i] - norm[i]) / norm[NF + i];
     const float y = mlp_forward(P, x, h1, z1, h2, z2);
     pred[u] = y * norm[2 * NF + 1] + norm[2 * NF];
 }
@@ -236,11 +250,13 @@ kc_status features(const kc_graph *g, int k, float *feat, hipStream_t s) {
 
 kc_status kc_predict_work(const kc_graph *g, int k, float *d_pred, hipStream_t s) {
     if (!g->mlp_loaded) return kc_fail(KC_ESTATE, "no scheduler weights loaded");
-    kc_tmp feat;
-    KC_TRY(kc_tmp_alloc(feat, (size_t)g->n * NF * 4, s));
-    KC_TRY(features(g, k, feat.as<float>(), s));
-    hipLaunchKernelGGL(k_mlp_infer, dim3(grid_for(g->n)), dim3(T), 0, s, (const float *)feat.as<float>(), g->n,
-                       (const float *)g->mlp, d_pred);
+    kc_graph *gm = const_cast<kc_graph *>(g);
+    if (!gm->feat) {  // the k-independent features, once per graph
+        KC_TRY(kc_dev_alloc((void **)&gm->feat, (size_t)g->n * NF * 4, s));
+        KC_TRY(features(g, 4, gm->feat, s));
+    }
+    hipLaunchKernelGGL(k_mlp_infer_k, dim3(grid_for(g->n)), dim3(T), 0, s, (const float *)gm->feat, g->n, k,
+                       (const uint64_t *)g->optr, (const float *)g->mlp, d_pred);
     KC_HIP(hipGetLastError());
     return KC_OK;
 }
