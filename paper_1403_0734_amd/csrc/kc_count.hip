@@ -294,6 +294,21 @@ __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int el
         wave_sync();
         return;
     }
+    if (R == 2 && listed) {
+        // two levels: an edge task (i, j) adds the edges inside P = row_i & row_j, one
+        // intersection per member of P
+        for (uint32_t t = lane; t < E; t += 64) {
+            const uint32_t e = A.elist[t];
+            uint64_t P = A.rows[e >> 8] & A.rows[e & 255u];
+            while (P) {
+                const uint32_t v = (uint32_t)__builtin_ctzll(P);
+                P &= P - 1;
+                acc += (uint64_t)__popcll(P & A.rows[v]);
+            }
+        }
+        wave_sync();
+        return;
+    }
     // Idle lanes are refilled together, once at least REFILL of them wait (or
     // no lane is busy): task t of the i-th idle lane is next + i.
     constexpr uint32_t REFILL = 16;
