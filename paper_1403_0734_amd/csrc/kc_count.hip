@@ -309,6 +309,25 @@ __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int el
         wave_sync();
         return;
     }
+    if (R == 3 && listed) {
+        // three levels: the same, one level deeper
+        for (uint32_t t = lane; t < E; t += 64) {
+            const uint32_t e = A.elist[t];
+            uint64_t P = A.rows[e >> 8] & A.rows[e & 255u];
+            while (P) {
+                const uint32_t v = (uint32_t)__builtin_ctzll(P);
+                P &= P - 1;
+                uint64_t Q = P & A.rows[v];
+                while (Q) {
+                    const uint32_t w = (uint32_t)__builtin_ctzll(Q);
+                    Q &= Q - 1;
+                    acc += (uint64_t)__popcll(Q & A.rows[w]);
+                }
+            }
+        }
+        wave_sync();
+        return;
+    }
     // Idle lanes are refilled together, once at least REFILL of them wait (or
     // no lane is busy): task t of the i-th idle lane is next + i.
     constexpr uint32_t REFILL = 16;
