@@ -1291,11 +1291,13 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                     }
                 }
             };
-            if (K >= 5) {
+            if (K >= 4) {
                 // Nodes are taken GRAB at a time.  Those with more than 64 candidates
                 // go one by one; the others are packed while their candidate sets
                 // sum to at most 64 nodes, side by side as the diagonal blocks of one
-                // local graph (no edge joins two blocks), counted in one pass.
+                // local graph (no edge joins two blocks), counted in one pass.  At k = 4
+                // a node's count is the number of edges inside its candidate set: each
+                // member lane counts its own, with no local graph built.
                 constexpr uint32_t GRAB = 16;
                 uint8_t *rs = reinterpret_cast<uint8_t *>(&A.members[0]);  // block starts
                 uint8_t *rt = rs + 64;                                      // block's slot in the grab
@@ -1356,7 +1358,11 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                             const uint64_t *rv = bm_row(bm, vn, W);
                             const uint32_t vlo = (vn + 1) >> 6;
                             uint32_t run = base;
-                            for (uint32_t l2 = lo0; l2 < W; ++l2) {
+                            if (K == 4) {
+                                for (uint32_t l2 = vlo; l2 < W; ++l2) acc += (uint64_t)__popcll(rv[l2] & ri[l2]);
+                                run = W;  // rows are not built
+                            }
+                            for (uint32_t l2 = K == 4 ? W : lo0; l2 < W; ++l2) {
                                 const uint64_t pw = ri[l2];
                                 if (l2 >= vlo) {
                                     uint64_t x = rv[l2] & pw;
@@ -1369,9 +1375,13 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                                 run += (uint32_t)__popcll(pw);
                             }
                         }
-                        A.rows[lane] = lrow;
-                        wave_sync();
-                        local_count<LC_REG_WG>(A, S, K - 2, acc);
+                        if (K > 4) {
+                            A.rows[lane] = lrow;
+                            wave_sync();
+                            local_count<LC_REG_WG>(A, S, K - 2, acc);
+                        } else {
+                            wave_sync();  // rs/rt are rewritten by the next pack
+                        }
                         cm &= ~fit;
                     }
                 }
