@@ -1554,6 +1554,53 @@ __global__ void k_stage_sizes(const uint64_t *optr, uint32_t n, uint32_t wd, uin
 
 }  // namespace
 
+kc_status kc_stage_queue(const kc_graph *g, const kc_queue &q, int wd, uint64_t *res, kc_tmp &lrows, kc_tmp &wbits,
+                         kc_tmp &woff, bool &cached) {
+    cached = false;
+    hipStream_t s = g->stream;
+    const uint32_t n = g->n;
+    // the staging pass runs the clique-size-3 kernels: their workgroup arena must hold
+    // every root the queue puts in the workgroup tier
+    if (q.count[1] && q.max_d[1] > kc_lds_dcap(g->device, 3)) return KC_OK;
+    KC_TRY(kc_tmp_alloc(woff, ((size_t)n + 1) * 8, s));
+    {
+        kc_tmp sizes;
+        KC_TRY(kc_tmp_alloc(sizes, (size_t)(n ? n : 1) * 8, s));
+        hipLaunchKernelGGL(k_stage_sizes, dim3((n + 255) / 256), dim3(256), 0, s, (const uint64_t *)g->optr, n,
+                           (uint32_t)wd, sizes.as<uint64_t>());
+        KC_HIP(hipGetLastError());
+        KC_TRY(kc_scan_excl_u64(sizes.as<uint64_t>(), woff.as<uint64_t>(), n, woff.as<uint64_t>() + n, s));
+    }
+    uint64_t *h = kc_pinned_scratch();
+    KC_HIP(hipMemcpyAsync(h, woff.as<uint64_t>() + n, 8, hipMemcpyDeviceToHost, s));
+    KC_TRY(kc_sync(s));
+    const uint64_t total = h[0];
+    size_t fr = 0, tot = 0;
+    KC_HIP(hipMemGetInfo(&fr, &tot));
+    if ((g->m + total) * 8 > fr / 2) return KC_OK;
+    KC_TRY(kc_tmp_alloc(lrows, (size_t)(g->m ? g->m : 1) * 8, s));
+    KC_TRY(kc_tmp_alloc(wbits, (size_t)(total ? total : 1) * 8, s));
+    kc_graph gs = *g;  // a view with the caches attached (owns nothing)
+    gs.lrows = lrows.as<uint64_t>();
+    gs.wbits = wbits.as<uint64_t>();
+    gs.woff = woff.as<uint64_t>();
+    kc_tmp gscr;
+    size_t slice_words = 0;
+    uint32_t scratch_blocks = 0;
+    KC_TRY(kc_count_scratch(g, q, 3, gscr, slice_words, scratch_blocks));
+    kc_count_args a;
+    a.k = 3;
+    a.store = 1;
+    const kc_status st = kc_count_launch(&gs, q, a, res, nullptr, 0, nullptr, gscr.as<uint64_t>(), slice_words,
+                                         scratch_blocks, s, nullptr);
+    gs.lrows = gs.wbits = gs.woff = nullptr;
+    gs.optr = nullptr;  // the copy must not look like an owner of anything
+    KC_TRY(st);
+    KC_TRY(kc_sync(s));
+    cached = true;
+    return KC_OK;
+}
+
 // Stage every root's G+(u) into the handle's cache (wave tier split at wd).
 // Leaves the handle uncached (staged = -1) when the cache would take more than
 // half of the free device memory.

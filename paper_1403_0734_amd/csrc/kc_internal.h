@@ -147,6 +147,14 @@ kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_a
                           size_t slice_words, uint32_t scratch_blocks, hipStream_t s,
                           hipEvent_t *tier_ev = nullptr);
 
+// Stage the G+(u) of the roots in queue q of graph g into caches allocated here
+// (rows for roots with out-degree <= wd, packed bitmaps above), enqueued on g's
+// stream with a result block the caller owns (KC_RES_WORDS words); cached is false
+// (and nothing is staged) when the caches would take more than half the free memory
+// or a workgroup-tier root does not fit the staging kernels' arena.
+kc_status kc_stage_queue(const kc_graph *g, const kc_queue &q, int wd, uint64_t *res, kc_tmp &lrows, kc_tmp &wbits,
+                         kc_tmp &woff, bool &cached);
+
 // Drop a cached batch plan that refers to the handle with this serial.
 void kc_batch_forget(uint64_t serial);
 
