@@ -256,7 +256,9 @@ __device__ __forceinline__ void st_set(uint64_t (&st)[N], int d, uint64_t v) {
     for (int i = 0; i < N; ++i) st[i] = d == i ? v : st[i];
 }
 
-template <int REGL, int NS>
+// SPREAD3: unlisted edges at R = 3 (below) are also shared out a fixed set per
+// lane rather than through the state machine.
+template <int REGL, bool SPREAD3, int NS>
 __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int ell, uint64_t &acc) {
     static_assert(REGL >= LC_LDS_FROM, "levels neither in registers nor in LDS");
     const uint32_t lane = kc_lane();
@@ -285,43 +287,52 @@ __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int el
         A.epre[lane] = ei - ce;
     }
     wave_sync();
-    if (R == 1 && listed) {
-        // one level: every edge task is a single intersection
-        for (uint32_t t = lane; t < E; t += 64) {
-            const uint32_t e = A.elist[t];
-            acc += (uint64_t)__popcll(A.rows[e >> 8] & A.rows[e & 255u]);
-        }
-        wave_sync();
-        return;
-    }
-    if (R == 2 && listed) {
-        // two levels: an edge task (i, j) adds the edges inside P = row_i & row_j, one
-        // intersection per member of P
-        for (uint32_t t = lane; t < E; t += 64) {
-            const uint32_t e = A.elist[t];
-            uint64_t P = A.rows[e >> 8] & A.rows[e & 255u];
-            while (P) {
-                const uint32_t v = (uint32_t)__builtin_ctzll(P);
-                P &= P - 1;
-                acc += (uint64_t)__popcll(P & A.rows[v]);
+    if (R <= 2 || (R == 3 && (listed || SPREAD3))) {
+        // Up to three levels below an edge: lane l takes edges l, l + 64, ...  An
+        // edge task (i, j) adds the (R+1)-cliques of the candidate set
+        // P = row_i & row_j: its size (R = 1), one intersection per member (R = 2),
+        // one per edge inside it (R = 3).  The edge is read from the list, or
+        // found from the row starts: lane r holds row r's first edge, and the
+        // rows starting in a batch of 64 edges are scanned once by the whole wave.
+        // Unlisted edges at R = 3 go to the state machine below unless SPREAD3:
+        // their subtrees can vary too much for a fixed share per lane (dense
+        // candidate sets in the workgroup tier), while the one-wave tier's small
+        // roots gain from the simpler loop.
+        const uint32_t start = ei - ce;
+        uint32_t r0 = 0;  // the row holding the batch's first edge
+        for (uint32_t b = 0; b < E; b += 64) {
+            const uint32_t t = b + lane;
+            uint64_t P;
+            if (listed) {
+                const uint32_t e = t < E ? A.elist[t] : 0u;
+                P = t < E ? A.rows[e >> 8] & A.rows[e & 255u] : 0ull;
+            } else {
+                uint32_t i = r0;
+                for (uint32_t x = r0 + 1; x < s; ++x) {
+                    const uint32_t sx = (uint32_t)__builtin_amdgcn_readlane((int)start, (int)x);
+                    if (sx >= b + 64) break;
+                    if (sx <= t) i = x;
+                }
+                r0 = (uint32_t)__builtin_amdgcn_readlane((int)i, 63);
+                const uint64_t ri = A.rows[i];
+                P = t < E ? ri & A.rows[select_bit(ri, t - A.epre[i])] : 0ull;
             }
-        }
-        wave_sync();
-        return;
-    }
-    if (R == 3 && listed) {
-        // three levels: the same, one level deeper
-        for (uint32_t t = lane; t < E; t += 64) {
-            const uint32_t e = A.elist[t];
-            uint64_t P = A.rows[e >> 8] & A.rows[e & 255u];
-            while (P) {
-                const uint32_t v = (uint32_t)__builtin_ctzll(P);
-                P &= P - 1;
-                uint64_t Q = P & A.rows[v];
-                while (Q) {
-                    const uint32_t w = (uint32_t)__builtin_ctzll(Q);
-                    Q &= Q - 1;
-                    acc += (uint64_t)__popcll(Q & A.rows[w]);
+            if (R == 1) {
+                acc += (uint64_t)__popcll(P);
+            } else {
+                while (P) {
+                    const uint32_t v = (uint32_t)__builtin_ctzll(P);
+                    P &= P - 1;
+                    uint64_t Q = P & A.rows[v];
+                    if (R == 2) {
+                        acc += (uint64_t)__popcll(Q);
+                    } else {
+                        while (Q) {
+                            const uint32_t w = (uint32_t)__builtin_ctzll(Q);
+                            Q &= Q - 1;
+                            acc += (uint64_t)__popcll(Q & A.rows[w]);
+                        }
+                    }
                 }
             }
         }
@@ -428,9 +439,49 @@ __device__ __forceinline__ void local_count2(LocalArea2<NS> &A, uint32_t s, int 
     const int R = ell - 2;
     const uint32_t incl = kc_wave_incl_u32(ca + cb);
     const uint32_t E = __shfl(incl, 63, 64);
-    A.epre[2 * lane] = incl - ca - cb;
-    A.epre[2 * lane + 1] = incl - cb;
+    const uint32_t sa = incl - ca - cb, sb = incl - cb;  // first edges of rows 2*lane, 2*lane+1
+    A.epre[2 * lane] = sa;
+    A.epre[2 * lane + 1] = sb;
     wave_sync();
+    if (R <= 2) {
+        // as in local_count: lane l takes edges l, l + 64, ..., each edge's row
+        // found from the row starts that fall in its batch of 64 edges
+        uint32_t r0 = 0;
+        for (uint32_t b = 0; b < E; b += 64) {
+            const uint32_t t = b + lane;
+            uint32_t i = r0;
+            for (uint32_t x = r0 + 1; x < s; ++x) {
+                const uint32_t sx = (uint32_t)__builtin_amdgcn_readlane((int)((x & 1u) ? sb : sa), (int)(x >> 1));
+                if (sx >= b + 64) break;
+                if (sx <= t) i = x;
+            }
+            r0 = (uint32_t)__builtin_amdgcn_readlane((int)i, 63);
+            uint64_t p0 = 0, p1 = 0;
+            if (t < E) {
+                const uint64_t r0w = A.rows[i][0], r1w = A.rows[i][1];
+                const uint32_t j = select_bit2(r0w, r1w, t - A.epre[i]);
+                p0 = r0w & A.rows[j][0];
+                p1 = r1w & A.rows[j][1];
+            }
+            if (R == 1) {
+                acc += (uint64_t)(__popcll(p0) + __popcll(p1));
+                continue;
+            }
+            while (p0 | p1) {
+                uint32_t v;
+                if (p0) {
+                    v = (uint32_t)__builtin_ctzll(p0);
+                    p0 &= p0 - 1;
+                } else {
+                    v = 64u + (uint32_t)__builtin_ctzll(p1);
+                    p1 &= p1 - 1;
+                }
+                acc += (uint64_t)(__popcll(p0 & A.rows[v][0]) + __popcll(p1 & A.rows[v][1]));
+            }
+        }
+        wave_sync();
+        return;
+    }
     constexpr uint32_t REFILL = 16;
     constexpr bool REG = NS <= LC_LDS_FROM;
     uint64_t st0[REG ? NS : 1], st1[REG ? NS : 1];
@@ -778,7 +829,7 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
             continue;
         }
         wave_sync();
-        local_count<LC_REG_WAVE>(sm.A, d, K - 1, acc);
+        local_count<LC_REG_WAVE, true>(sm.A, d, K - 1, acc);
 
         if (p.per_root) {
             const uint64_t q = kc_wave_sum_checked(acc, &ovf);
@@ -1224,7 +1275,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                 }
                 if (pc <= 64) {
                     const uint32_t sN = compact_local(ri, lo0, W, bm, W, A);
-                    local_count<LC_REG_WG>(A, sN, K - 2, acc);
+                    local_count<LC_REG_WG, false>(A, sN, K - 2, acc);
                     return;
                 }
                 if (K >= 5 && pc <= 128) {
@@ -1281,7 +1332,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                         wave_sync();
                     } else if (cpc <= 64) {
                         const uint32_t sN = compact_local(nxt, clo, W, bm, W, A);
-                        local_count<LC_REG_WG>(A, sN, cn, acc);
+                        local_count<LC_REG_WG, false>(A, sN, cn, acc);
                     } else if (K >= 5 && cpc <= 128) {
                         const uint32_t sN = compact_local2(nxt, clo, W, bm, W, A2);
                         local_count2(A2, sN, cn, acc);
@@ -1378,7 +1429,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                         if (K > 4) {
                             A.rows[lane] = lrow;
                             wave_sync();
-                            local_count<LC_REG_WG>(A, S, K - 2, acc);
+                            local_count<LC_REG_WG, false>(A, S, K - 2, acc);
                         } else {
                             wave_sync();  // rs/rt are rewritten by the next pack
                         }
