@@ -101,7 +101,7 @@ void kc_graph_destroy(kc_graph *g) {
     if (!g) return;
     kc_batch_forget(g->serial);
     void *bufs[] = {g->rowptr, g->col,  g->deg, g->ukeys, g->optr,  g->ocol,  g->rank2id, g->id2rank,
-                    g->mlp,    g->d_res, g->dq,  g->tri,   g->lrows, g->wbits, g->woff, g->feat};
+                    g->mlp,    g->d_res, g->dq,  g->tri,   g->lrows, g->wbits, g->woff, g->feat, g->wq, g->wedges};
     for (void *b : bufs)
         kc_cache_free(b, g->stream);
     (void)kc_sync(g->stream);

@@ -154,6 +154,7 @@ struct CountParams {
     // staged G+(u) cache of the handle: wave-tier rows, larger roots' bitmaps
     uint64_t *lrows;
     uint64_t *wbits;
+    uint32_t *wedges;           // staging: edges of each workgroup-tier G+(u), by rank (optional)
     const uint64_t *woff;
 };
 
@@ -1105,6 +1106,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
             u = p.queue[cb + ci];
         }
         ++ci;
+        if (u == 0xFFFFFFFFu) continue;  // padding of an item list
         const uint64_t base = p.optr[u];
         uint32_t d = (uint32_t)(p.optr[u + 1] - base);
 
@@ -1247,7 +1249,21 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
             // keep the staged bitmap for later counts
             __syncthreads();
             uint64_t *dst = p.wbits + p.woff[u];
-            for (uint64_t w = tid; w < words; w += WG) dst[w] = bm[w];
+            uint32_t ec = 0;
+            for (uint64_t w = tid; w < words; w += WG) {
+                dst[w] = bm[w];
+                ec += (uint32_t)__popcll(bm[w]);
+            }
+            if (p.wedges) {  // the edge count orders later counts' work (heaviest first)
+                ec = kc_wave_sum_u32(ec);
+                if (lane == 0) s_red[wave] = ec;
+                __syncthreads();
+                if (tid == 0) {
+                    uint64_t e = 0;
+                    for (int w = 0; w < WAVES; ++w) e += s_red[w];
+                    p.wedges[u] = e > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)e;
+                }
+            }
             __syncthreads();
             continue;
         }
@@ -1349,16 +1365,26 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                 // local graph (no edge joins two blocks), counted in one pass.  At k = 4
                 // a node's count is the number of edges inside its candidate set: each
                 // member lane counts its own, with no local graph built.
+                // Grabs of a split root's item shrink as its nodes run out (guided
+                // self-scheduling: an eighth of what is left, 2 to 16 nodes), so the
+                // waves of the block finish together; whole roots take 16 at a time.
                 constexpr uint32_t GRAB = 16;
+                const uint32_t nodes = part < d ? (d - part + parts - 1) / parts : 0u;
                 uint8_t *rs = reinterpret_cast<uint8_t *>(&A.members[0]);  // block starts
                 uint8_t *rt = rs + 64;                                      // block's slot in the grab
                 for (;;) {
-                    uint32_t j0 = 0;
-                    if (lane == 0) j0 = atomicAdd(&s_misc[2], GRAB);
+                    uint32_t j0 = 0, gsz = 0;
+                    if (lane == 0) {
+                        const uint32_t seen = __hip_atomic_load(&s_misc[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        const uint32_t left = seen < nodes ? nodes - seen : 0u;
+                        gsz = parts == 1 ? GRAB : (left / 8u < 2u ? 2u : (left / 8u > GRAB ? GRAB : left / 8u));
+                        j0 = atomicAdd(&s_misc[2], gsz);
+                    }
                     j0 = __shfl(j0, 0, 64);
+                    gsz = __shfl(gsz, 0, 64);
                     if (part + j0 * parts >= d) break;
                     const uint32_t my_i = part + (j0 + lane) * parts;
-                    const bool valid = lane < GRAB && my_i < d;
+                    const bool valid = lane < gsz && my_i < d;
                     uint32_t my_pc = 0;
                     if (valid) {
                         const uint64_t *ri = bm_row(bm, my_i, W);
@@ -1661,7 +1687,12 @@ kc_status kc_stage(kc_graph *g, int wd) {
     kc_cache_free(g->lrows, s);
     kc_cache_free(g->wbits, s);
     kc_cache_free(g->woff, s);
+    kc_cache_free(g->wq, s);
+    kc_cache_free(g->wedges, s);
     g->lrows = g->wbits = g->woff = nullptr;
+    g->wq = nullptr;
+    g->wedges = nullptr;
+    g->wq_ready = 0;
     g->staged = 0;
     const uint32_t n = g->n;
     uint64_t *woff = nullptr;
@@ -1687,6 +1718,7 @@ kc_status kc_stage(kc_graph *g, int wd) {
         return KC_OK;
     }
     g->woff = woff;
+    KC_TRY(kc_dev_alloc((void **)&g->wedges, (size_t)(n ? n : 1) * 4, s));
     KC_TRY(kc_dev_alloc((void **)&g->lrows, (size_t)(g->m ? g->m : 1) * 8, s));
     KC_TRY(kc_dev_alloc((void **)&g->wbits, (size_t)(total ? total : 1) * 8, s));
     kc_queue q;
@@ -1766,6 +1798,7 @@ kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_a
     p.lrows = g->lrows;
     p.wbits = g->wbits;
     p.woff = g->woff;
+    p.wedges = g->wedges;
     uint32_t *cursors = (uint32_t *)(res + 2);
     if (a.store) {
         // staging into the cache does not depend on k
@@ -1802,12 +1835,8 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
     const uint32_t dcap = kc_lds_dcap(g->device, a.k);
 
     KC_HIP(hipEventRecord(g->ev[0], s));
-    kc_queue q;
-    KC_TRY(kc_build_queue(g, a.k, a.policy, dcap, q));
-    KC_HIP(hipEventRecord(g->ev[1], s));
-    if (a.per_root) KC_HIP(hipMemsetAsync(a.per_root, 0, (size_t)g->n * sizeof(uint64_t), s));
-    // the first count on a handle stages every G+(u) once; later counts read it
-    // (KC_STAGE_CACHE=0 stages per call instead)
+    // the first count on a handle stages every G+(u) once (timed with the
+    // schedule); later counts read it (KC_STAGE_CACHE=0 stages per call instead)
     kc_count_args ac = a;
     const char *sc = getenv("KC_STAGE_CACHE");
     if (!(sc && sc[0] == '0')) {
@@ -1817,6 +1846,10 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
         KC_TRY(kc_stage(gm, wd));
         ac.cached = gm->staged == 1;
     }
+    kc_queue q;
+    KC_TRY(kc_build_queue(g, a.k, a.policy, dcap, q));
+    KC_HIP(hipEventRecord(g->ev[1], s));
+    if (a.per_root) KC_HIP(hipMemsetAsync(a.per_root, 0, (size_t)g->n * sizeof(uint64_t), s));
     kc_tmp gscr;
     size_t slice_words = 0;
     uint32_t scratch_blocks = 0;

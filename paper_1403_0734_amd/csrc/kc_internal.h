@@ -104,6 +104,15 @@ struct kc_graph {
     int stage_wd = 0;
     uint64_t *lrows = nullptr, *wbits = nullptr, *woff = nullptr;
 
+    // Workgroup-tier items for counts from k = 5 on (degree policy, staged
+    // handles): the tier's roots by edges of G+(u), heaviest first, the heaviest
+    // split over several items (rank << 32 | part << 16 | parts).  Built for the
+    // tier span [wq_first, wq_first + wq_roots) of the degree queue.
+    int wq_ready = 0;
+    uint32_t wq_first = 0, wq_roots = 0, wq_count = 0;
+    uint64_t *wq = nullptr;
+    uint32_t *wedges = nullptr;  // edges of G+(u) by rank, written when staging (roots above stage_wd)
+
     uint64_t serial = 0;  // unique per handle (batch plans are keyed by it)
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     float t_schedule = 0.f, t_count = 0.f, t_total = 0.f;

@@ -124,6 +124,146 @@ __global__ void k_split_emit(const uint32_t *q, uint32_t cnt, const uint32_t *pa
         items[off[i] + pt] = ((uint64_t)q[i] << 32) | ((uint64_t)pt << 16) | (uint64_t)np;
 }
 
+// Split of the workgroup tier (degree policy): a root of out-degree d above dsplit
+// is cut into parts(d) = min(ceil(d / 2^sh), 64) items.
+__host__ __device__ inline uint32_t degree_parts(uint64_t d, uint32_t dsplit, uint32_t sh) {
+    if (d <= dsplit) return 1u;
+    const uint64_t np = (d + (1ull << sh) - 1) >> sh;
+    return np > 64 ? 64u : (uint32_t)np;
+}
+
+__global__ void k_degree_parts(const uint32_t *q, uint32_t cnt, const uint64_t *optr, uint32_t dsplit, uint32_t sh,
+                               uint32_t *parts) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    const uint32_t u = q[i];
+    parts[i] = degree_parts(optr[u + 1] - optr[u], dsplit, sh);
+}
+
+// Work items of the workgroup tier (staged handles), three grid passes and no
+// host round trip:
+//   1. the sum of the roots' edge counts of G+(u) (kept when staging);
+//   2. items per root, ceil(edges / target) with target the smaller of four times
+//      the mean and 1/1024 of the total (at least 1), at most min(64, out-degree);
+//      items per 8-bit edge bucket;
+//   3. items written bucket by bucket, heaviest bucket first (a counting sort:
+//      longest-processing-time order at bucket resolution), the list padded to
+//      its bound with skipped items.
+// Items: sum of parts <= cnt + total / target <= cnt + max(cnt / 4, 1024).
+struct WqAux {
+    double sum;
+    uint32_t bcnt[256];  // items per bucket
+    uint32_t bcur[256];  // items placed per bucket
+};
+
+__global__ void k_wq_clear(WqAux *a) {
+    const uint32_t t = threadIdx.x;
+    if (t == 0) a->sum = 0.0;
+    for (uint32_t i = t; i < 256; i += blockDim.x) {
+        a->bcnt[i] = 0;
+        a->bcur[i] = 0;
+    }
+}
+
+__global__ void k_edge_sum(const uint32_t *q, uint32_t cnt, const uint32_t *wedges, WqAux *a) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t c = i < cnt ? wedges[q[i]] : 0u;
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63u) == 0 && c) atomicAdd(&a->sum, (double)c);
+}
+
+// 8-bit bucket of an edge count, more edges first: 255 - (8 * floor(log2 c) + the
+// next three bits of c).
+__device__ __forceinline__ uint32_t edge_bucket(uint32_t c) {
+    if (c == 0) return 255u;
+    const uint32_t e = 31u - (uint32_t)__builtin_clz(c);
+    const uint32_t m = e >= 3 ? (c >> (e - 3)) & 7u : (c << (3 - e)) & 7u;
+    const uint32_t key = 8u * e + m;
+    return 255u - (key > 255u ? 255u : key);
+}
+
+__global__ void k_root_parts(const uint32_t *q, const uint32_t *wedges, uint32_t cnt, const uint64_t *optr, WqAux *a,
+                             uint32_t *parts) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    const double tot = a->sum;
+    double target = 4.0 * tot / (double)cnt;
+    if (tot / 1024.0 < target) target = tot / 1024.0;
+    if (target < 1.0) target = 1.0;
+    const uint32_t u = q[i];
+    const uint64_t d = optr[u + 1] - optr[u];
+    const uint32_t c = wedges[u];
+    double np = ceil((double)c / target);
+    const double cap = d < 64 ? (double)(d ? d : 1) : 64.0;
+    np = np < 1.0 ? 1.0 : (np > cap ? cap : np);
+    parts[i] = (uint32_t)np;
+    atomicAdd(&a->bcnt[edge_bucket(c)], (uint32_t)np);
+}
+
+constexpr uint32_t WQ_SKIP = 0xFFFFFFFFu;
+
+__global__ void k_emit_items(const uint32_t *q, const uint32_t *wedges, const uint32_t *parts, uint32_t cnt,
+                             WqAux *a, uint32_t bound, uint64_t *items) {
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t s_total;
+    const uint32_t tid = threadIdx.x;
+    if (tid < 64) {  // exclusive scan of the 256 bucket counts, four per lane
+        const uint32_t h0 = a->bcnt[4 * tid], h1 = a->bcnt[4 * tid + 1], h2 = a->bcnt[4 * tid + 2],
+                       h3 = a->bcnt[4 * tid + 3];
+        const uint32_t t4 = h0 + h1 + h2 + h3;
+        const uint32_t incl = kc_wave_incl_u32(t4);
+        const uint32_t b0 = incl - t4;
+        base[4 * tid] = b0;
+        base[4 * tid + 1] = b0 + h0;
+        base[4 * tid + 2] = b0 + h0 + h1;
+        base[4 * tid + 3] = b0 + h0 + h1 + h2;
+        if (tid == 63) s_total = incl;
+    }
+    __syncthreads();
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + tid; i < cnt; i += stride) {
+        const uint32_t u = q[i], b = edge_bucket(wedges[u]), np = parts[i];
+        const uint32_t off = base[b] + atomicAdd(&a->bcur[b], np);
+        for (uint32_t pt = 0; pt < np; ++pt)
+            if (off + pt < bound) items[off + pt] = ((uint64_t)u << 32) | ((uint64_t)pt << 16) | (uint64_t)np;
+    }
+    for (size_t x = s_total + (size_t)blockIdx.x * blockDim.x + tid; x < bound; x += stride)
+        items[x] = (uint64_t)WQ_SKIP << 32;
+}
+
+// Bound of the item count; the list is padded to it.
+inline uint32_t work_items_bound(uint32_t cnt) {
+    const uint32_t extra = (cnt + 3) / 4 > 1024u ? (cnt + 3) / 4 : 1024u;
+    return cnt + extra + 1;
+}
+
+kc_status build_work_items(kc_graph *g, uint32_t first, uint32_t cnt) {
+    hipStream_t s = g->stream;
+    kc_cache_free(g->wq, s);
+    g->wq = nullptr;
+    g->wq_count = 0;
+    g->wq_ready = 0;
+    const uint32_t bound = work_items_bound(cnt);
+    const uint32_t *q = g->dq + first;
+    kc_tmp aux, parts;
+    KC_TRY(kc_tmp_alloc(aux, sizeof(WqAux), s));
+    KC_TRY(kc_tmp_alloc(parts, (size_t)cnt * 4, s));
+    KC_TRY(kc_dev_alloc((void **)&g->wq, (size_t)bound * 8, s));
+    WqAux *a = aux.as<WqAux>();
+    hipLaunchKernelGGL(k_wq_clear, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_edge_sum, dim3(grid_for(cnt)), dim3(T), 0, s, q, cnt, (const uint32_t *)g->wedges, a);
+    hipLaunchKernelGGL(k_root_parts, dim3(grid_for(cnt)), dim3(T), 0, s, q, (const uint32_t *)g->wedges, cnt,
+                       (const uint64_t *)g->optr, a, parts.as<uint32_t>());
+    hipLaunchKernelGGL(k_emit_items, dim3(grid_for(bound)), dim3(T), 0, s, q, (const uint32_t *)g->wedges,
+                       (const uint32_t *)parts.as<uint32_t>(), cnt, a, bound, g->wq);
+    KC_HIP(hipGetLastError());
+    g->wq_count = bound;
+    g->wq_first = first;
+    g->wq_roots = cnt;
+    g->wq_ready = 1;
+    return KC_OK;
+}
+
 kc_status build_degree_cache(kc_graph *g, uint32_t wd) {
     hipStream_t s = g->stream;
     if (g->dq) {
@@ -242,6 +382,47 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
             off += (uint32_t)hist[d];
         }
         if (off != q.count[1]) q.wg_ncls = 0;  // not a plain degree order: one launch
+        // From k = 5 on, the heaviest roots of the tier take most of its time, one
+        // workgroup each: roots above twice the one-wave bound are split over
+        // several items (Section 7, the (u, v) split), one per 32 first-level
+        // nodes (64 at k = 5); item p takes the nodes p, p + parts, ...
+        // With the staged cache, the tier is ordered by the edges of G+(u) instead
+        // (a far better guess at a root's work than its out-degree; heaviest first,
+        // longest-processing-time order) and split by that guess.
+        const char *wo = getenv("KC_WORK_ORDER");
+        if (k >= 5 && q.count[1] && g->staged == 1 && g->stage_wd == wd && g->wedges && !(wo && wo[0] == '0')) {
+            const uint32_t first = (uint32_t)(q.ptr[1] - g->dq);
+            if (!g->wq_ready || g->wq_first != first || g->wq_roots != q.count[1])
+                KC_TRY(build_work_items(gm, first, q.count[1]));
+            q.wg_items = g->wq;
+            q.wg_item_count = g->wq_count;
+            return KC_OK;
+        }
+        // KC_DEGREE_SPLIT: 0 turns the split off, n > 0 sets 2^n nodes per item from k = 6 on
+        const char *se = getenv("KC_DEGREE_SPLIT");
+        const int sn = se ? atoi(se) : 6;
+        if (k >= 5 && q.count[1] && sn > 0 && sn < 16) {
+            const uint32_t dsplit = 2u * (uint32_t)wd, sh = (uint32_t)sn + (k >= 6 ? 0u : 1u);
+            uint64_t nitems = 0;
+            for (uint32_t d = (uint32_t)wd + 1; d <= top; ++d) nitems += hist[d] * degree_parts(d, dsplit, sh);
+            const uint32_t c1 = q.count[1];
+            if (nitems > c1 && nitems < (1ull << 32)) {
+                kc_tmp parts, offs;
+                KC_TRY(kc_tmp_alloc(parts, (size_t)c1 * 4, s));
+                KC_TRY(kc_tmp_alloc(offs, (size_t)c1 * 4, s));
+                KC_TRY(kc_tmp_alloc(q.items_buf, (size_t)nitems * 8, s));
+                hipLaunchKernelGGL(k_degree_parts, dim3(grid_for(c1)), dim3(T), 0, s, q.ptr[1], c1,
+                                   (const uint64_t *)g->optr, dsplit, sh, parts.as<uint32_t>());
+                KC_HIP(hipGetLastError());
+                KC_TRY(kc_scan_excl_u32(parts.as<uint32_t>(), offs.as<uint32_t>(), c1, nullptr, s));
+                hipLaunchKernelGGL(k_split_emit, dim3(grid_for(c1)), dim3(T), 0, s, q.ptr[1], c1,
+                                   (const uint32_t *)parts.as<uint32_t>(), (const uint32_t *)offs.as<uint32_t>(),
+                                   q.items_buf.as<uint64_t>());
+                KC_HIP(hipGetLastError());
+                q.wg_items = q.items_buf.as<uint64_t>();
+                q.wg_item_count = (uint32_t)nitems;
+            }
+        }
         return KC_OK;
     }
 

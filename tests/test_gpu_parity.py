@@ -172,6 +172,38 @@ def test_staged_cache_and_per_call_staging(monkeypatch, cache):
         _close(h)
 
 
+ITEM_MODES = {
+    "edge-ordered items": {},
+    "degree split": {"KC_WORK_ORDER": "0"},
+    "degree split, per-call staging": {"KC_STAGE_CACHE": "0", "KC_DEGREE_SPLIT": "5"},
+    "whole roots": {"KC_WORK_ORDER": "0", "KC_DEGREE_SPLIT": "0"},
+}
+
+
+@pytest.mark.parametrize("mode", sorted(ITEM_MODES))
+def test_workgroup_items(monkeypatch, mode):
+    """The workgroup tier from k = 5 on, as whole roots, split by out-degree, or
+    ordered and split by the edges of G+(u) (padded item list): exact totals,
+    per-root counts (split roots add their parts) and colourings."""
+    for key, val in ITEM_MODES[mode].items():
+        monkeypatch.setenv(key, val)
+    for el in [SMALL[2], SMALL[12], MULTI_TILE[0]]:
+        og = O.OracleGraph.from_edgelist(el)
+        h = device_graph(el)
+        ks = [k for k in bounded_ks(og, 3, 8, budget=5e6) if k >= 5]
+        for k in ks:
+            announce(f"items {mode} {el.name} k={k}")
+            assert K.kc_count(h, k) == og.count(k), (el.name, k)
+        if ks:
+            k = ks[0]
+            c, _ = per_root(h, el.n, k)
+            assert np.array_equal(c, og.count_per_root(k)), (el.name, k)
+            for scheme in (K.KC_COLOR_PER_ROOT, K.KC_COLOR_GLOBAL):
+                e = K.kc_count_colored(h, k, 2, 5, scheme)
+                assert e.raw == og.count_colored(k, 2, 5, scheme), (el.name, k, scheme)
+        _close(h)
+
+
 def test_repeat_runs_identical():
     el = SMALL[12]
     h = device_graph(el)
