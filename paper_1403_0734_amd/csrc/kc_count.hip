@@ -259,6 +259,29 @@ __device__ __forceinline__ void st_set(uint64_t (&st)[N], int d, uint64_t v) {
 
 // SPREAD3: unlisted edges at R = 3 (below) are also shared out a fixed set per
 // lane rather than through the state machine.
+// Edges inside the node set P of a one-word local graph: sum over v in P of
+// |P_{>v} & row_v|.  Four members per step, so that four row reads are in flight
+// at once (a member past the end reads row 0 and adds nothing: its remainder is 0).
+__device__ __forceinline__ uint32_t edges_inside(uint64_t P, const uint64_t *rows) {
+    uint32_t c = 0;
+    while (P) {
+        const uint32_t v0 = (uint32_t)__builtin_ctzll(P);
+        P &= P - 1;
+        const uint64_t P1 = P;
+        const uint32_t v1 = P ? (uint32_t)__builtin_ctzll(P) : 0u;
+        P &= P - 1;
+        const uint64_t P2 = P;
+        const uint32_t v2 = P ? (uint32_t)__builtin_ctzll(P) : 0u;
+        P &= P - 1;
+        const uint64_t P3 = P;
+        const uint32_t v3 = P ? (uint32_t)__builtin_ctzll(P) : 0u;
+        P &= P - 1;
+        const uint64_t r0 = rows[v0], r1 = rows[v1], r2 = rows[v2], r3 = rows[v3];
+        c += (uint32_t)(__popcll(P1 & r0) + __popcll(P2 & r1) + __popcll(P3 & r2) + __popcll(P & r3));
+    }
+    return c;
+}
+
 template <int REGL, bool SPREAD3, int NS>
 __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int ell, uint64_t &acc) {
     static_assert(REGL >= LC_LDS_FROM, "levels neither in registers nor in LDS");
@@ -320,20 +343,13 @@ __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int el
             }
             if (R == 1) {
                 acc += (uint64_t)__popcll(P);
+            } else if (R == 2) {
+                acc += edges_inside(P, A.rows);
             } else {
                 while (P) {
                     const uint32_t v = (uint32_t)__builtin_ctzll(P);
                     P &= P - 1;
-                    uint64_t Q = P & A.rows[v];
-                    if (R == 2) {
-                        acc += (uint64_t)__popcll(Q);
-                    } else {
-                        while (Q) {
-                            const uint32_t w = (uint32_t)__builtin_ctzll(Q);
-                            Q &= Q - 1;
-                            acc += (uint64_t)__popcll(Q & A.rows[w]);
-                        }
-                    }
+                    acc += edges_inside(P & A.rows[v], A.rows);
                 }
             }
         }
