@@ -1627,6 +1627,13 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
         uint32_t blocks = (q.count[0] + WAVES - 1) / WAVES;
         const uint32_t cap = (uint32_t)di.cus * (uint32_t)(tu.wave_blocks_per_cu > 0 ? tu.wave_blocks_per_cu : 8);
         if (blocks > cap) blocks = cap;
+        // chunk size follows the work per root: staging (reads every out-list) takes
+        // half-size chunks, counts from the cache at k <= 5 (a few cheap passes per
+        // chunk) larger ones, so that fewer queue fetches stall the wave
+        const uint32_t cd = base.chunk_div;
+        if (MODE == MODE_STORE) p.chunk_div = cd * 2;
+        else if (MODE == MODE_CACHED && K <= 4) p.chunk_div = cd / 4 ? cd / 4 : 1;
+        else if (MODE == MODE_CACHED && K == 5) p.chunk_div = cd / 2 ? cd / 2 : 1;
         hipLaunchKernelGGL((k_count_wave<K, MODE>), dim3(blocks), dim3(WG), 0, s, p);
     }
     if (ev) (void)hipEventRecord(ev[3], s);
@@ -1721,10 +1728,19 @@ kc_status kc_stage(kc_graph *g, int wd) {
         KC_HIP(hipGetLastError());
         KC_TRY(kc_scan_excl_u64(sizes.as<uint64_t>(), woff, n, woff + n, s));
     }
-    uint64_t *h = kc_pinned_scratch();
-    KC_HIP(hipMemcpyAsync(h, woff + n, 8, hipMemcpyDeviceToHost, s));
-    KC_TRY(kc_sync(s));
-    const uint64_t total = h[0];
+    // the staging pass runs over the degree queue; its out-degree histogram (on
+    // the host) also gives the cache size without reading the scan back
+    kc_queue q;
+    KC_TRY(kc_build_queue(g, 3, KC_SCHED_DEGREE, kc_lds_dcap(g->device, 3), q));
+    uint64_t total = 0;
+    if (g->dq_ready && g->dq_wd == wd && g->dq_hist) {
+        for (uint32_t d = (uint32_t)wd + 1; d <= g->max_outdeg; ++d) total += g->dq_hist[d] * tri_words(d);
+    } else {
+        uint64_t *h = kc_pinned_scratch();
+        KC_HIP(hipMemcpyAsync(h, woff + n, 8, hipMemcpyDeviceToHost, s));
+        KC_TRY(kc_sync(s));
+        total = h[0];
+    }
     size_t fr = 0, tot = 0;
     KC_HIP(hipMemGetInfo(&fr, &tot));
     if ((g->m + total) * 8 > fr / 2) {
@@ -1737,8 +1753,6 @@ kc_status kc_stage(kc_graph *g, int wd) {
     KC_TRY(kc_dev_alloc((void **)&g->wedges, (size_t)(n ? n : 1) * 4, s));
     KC_TRY(kc_dev_alloc((void **)&g->lrows, (size_t)(g->m ? g->m : 1) * 8, s));
     KC_TRY(kc_dev_alloc((void **)&g->wbits, (size_t)(total ? total : 1) * 8, s));
-    kc_queue q;
-    KC_TRY(kc_build_queue(g, 3, KC_SCHED_DEGREE, kc_lds_dcap(g->device, 3), q));
     kc_tmp gscr;
     size_t slice_words = 0;
     uint32_t scratch_blocks = 0;

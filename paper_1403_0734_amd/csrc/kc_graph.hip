@@ -246,10 +246,11 @@ kc_status kc_canonicalise(kc_graph *g, const uint32_t *d_src, const uint32_t *d_
         hipLaunchKernelGGL(k_make_keys, dim3(grid_for(N)), dim3(T), 0, s, d_src, d_dst, N, n, B, sentinel,
                            keys.as<uint64_t>(), err.as<uint32_t>());
         KC_HIP(hipGetLastError());
-        KC_TRY(kc_radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), N, 0, 2 * B, s));
+        uint64_t *sk = nullptr;  // the sorted keys (either buffer)
+        KC_TRY(kc_radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), N, 0, 2 * B, s, &sk));
         KC_TRY(kc_tmp_alloc(flag, N * sizeof(uint32_t), s));
         KC_TRY(kc_tmp_alloc(pos, N * sizeof(uint32_t), s));
-        hipLaunchKernelGGL(k_unique_flags, dim3(grid_for(N)), dim3(T), 0, s, keys.as<uint64_t>(), N, sentinel,
+        hipLaunchKernelGGL(k_unique_flags, dim3(grid_for(N)), dim3(T), 0, s, (const uint64_t *)sk, N, sentinel,
                            flag.as<uint32_t>());
         KC_HIP(hipGetLastError());
         KC_TRY(kc_scan_excl_u32(flag.as<uint32_t>(), pos.as<uint32_t>(), N, total.as<uint32_t>(), s));
@@ -261,8 +262,8 @@ kc_status kc_canonicalise(kc_graph *g, const uint32_t *d_src, const uint32_t *d_
         M = h[1];
         // the unique edges stay on the handle: orientation and the symmetric CSR read them
         KC_TRY(kc_dev_alloc((void **)&g->ukeys, (size_t)(M ? M : 1) * sizeof(uint64_t), s));
-        hipLaunchKernelGGL(k_compact_u64, dim3(grid_for(N)), dim3(T), 0, s, keys.as<uint64_t>(), flag.as<uint32_t>(),
-                           pos.as<uint32_t>(), N, g->ukeys);
+        hipLaunchKernelGGL(k_compact_u64, dim3(grid_for(N)), dim3(T), 0, s, (const uint64_t *)sk,
+                           flag.as<uint32_t>(), pos.as<uint32_t>(), N, g->ukeys);
         KC_HIP(hipGetLastError());
         if (M) KC_TRY(degrees(g->ukeys, M, B, mask, n, g->deg, s));
     }
@@ -326,18 +327,18 @@ kc_status kc_orient_impl(kc_graph *g) {
     KC_TRY(kc_tmp_alloc(maxd, sizeof(uint32_t), s));
     KC_HIP(hipMemsetAsync(maxd.p, 0, sizeof(uint32_t), s));
     const size_t m = g->m;
+    uint64_t *sorted = nullptr;
     if (m > 0) {
         KC_TRY(kc_tmp_alloc(okeys, m * sizeof(uint64_t), s));
         KC_TRY(kc_tmp_alloc(otmp, m * sizeof(uint64_t), s));
         hipLaunchKernelGGL(k_orient_pairs, dim3(grid_for(m)), dim3(T), 0, s, (const uint64_t *)g->ukeys, m, B, mask,
                            (const uint32_t *)g->id2rank, okeys.as<uint64_t>());
         KC_HIP(hipGetLastError());
-        KC_TRY(kc_radix_sort_u64(okeys.as<uint64_t>(), otmp.as<uint64_t>(), m, 0, 2 * B, s));
-        hipLaunchKernelGGL(k_low_bits, dim3(grid_for(m)), dim3(T), 0, s, (const uint64_t *)okeys.as<uint64_t>(), m,
-                           mask, g->ocol);
+        KC_TRY(kc_radix_sort_u64(okeys.as<uint64_t>(), otmp.as<uint64_t>(), m, 0, 2 * B, s, &sorted));
+        hipLaunchKernelGGL(k_low_bits, dim3(grid_for(m)), dim3(T), 0, s, (const uint64_t *)sorted, m, mask, g->ocol);
         KC_HIP(hipGetLastError());
     }
-    KC_TRY(rows_from_sorted(okeys.as<uint64_t>(), m, B, n, g->optr, s));
+    KC_TRY(rows_from_sorted(sorted, m, B, n, g->optr, s));
     hipLaunchKernelGGL(k_row_lengths, dim3(rowlen_grid(n)), dim3(T), 0, s, (const uint64_t *)g->optr, n,
                        (uint32_t *)nullptr, maxd.as<uint32_t>());
     KC_HIP(hipGetLastError());

@@ -123,9 +123,11 @@ struct kc_graph {
 // Device-wide primitives (kc_prims.hip)
 kc_status kc_scan_excl_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *d_total, hipStream_t s);
 kc_status kc_scan_excl_u64(const uint64_t *in, uint64_t *out, size_t n, uint64_t *d_total, hipStream_t s);
-// Stable LSD radix sort of 64-bit keys on bits [bit_lo, bit_hi).  Sorted keys end
-// in *keys (tmp is a same-sized buffer).
-kc_status kc_radix_sort_u64(uint64_t *keys, uint64_t *tmp, size_t n, int bit_lo, int bit_hi, hipStream_t s);
+// Stable LSD radix sort of 64-bit keys on bits [bit_lo, bit_hi).  tmp is a
+// same-sized buffer.  The sorted keys end in keys, or, when `sorted` is given,
+// in whichever of the two buffers the last pass wrote (*sorted), with no copy.
+kc_status kc_radix_sort_u64(uint64_t *keys, uint64_t *tmp, size_t n, int bit_lo, int bit_hi, hipStream_t s,
+                            uint64_t **sorted = nullptr);
 
 // Ingest and orientation (kc_graph.hip)
 kc_status kc_canonicalise(kc_graph *g, const uint32_t *d_src, const uint32_t *d_dst);

@@ -188,10 +188,17 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint64_t *in, u
     s_start[tid] = before + inc - c;
     s_gbase[tid] = dbefore + dinc - dt + offs[(size_t)tid * nblocks + blockIdx.x];
     const size_t base = (size_t)blockIdx.x * RS_TILE;
+    uint64_t kk[RS_ITEMS];  // the tile's keys, all loads issued before the ranking
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const size_t i = base + (size_t)r * RS_THREADS + tid;
+        kk[r] = i < n ? in[i] : 0ull;
+    }
+#pragma unroll
     for (int r = 0; r < RS_ITEMS; ++r) {
         const size_t i = base + (size_t)r * RS_THREADS + tid;
         const bool valid = i < n;
-        const uint64_t key = valid ? in[i] : 0ull;
+        const uint64_t key = kk[r];
         const uint32_t d = (uint32_t)(key >> shift) & 255u;
 #pragma unroll
         for (int w = 0; w < RS_THREADS / 64; ++w) s_w[w][tid] = 0;
@@ -230,7 +237,9 @@ kc_status kc_scan_excl_u64(const uint64_t *in, uint64_t *out, size_t n, uint64_t
     return scan_excl<uint64_t>(in, out, n, d_total, s);
 }
 
-kc_status kc_radix_sort_u64(uint64_t *keys, uint64_t *tmp, size_t n, int bit_lo, int bit_hi, hipStream_t s) {
+kc_status kc_radix_sort_u64(uint64_t *keys, uint64_t *tmp, size_t n, int bit_lo, int bit_hi, hipStream_t s,
+                            uint64_t **sorted) {
+    if (sorted) *sorted = keys;
     if (n <= 1 || bit_hi <= bit_lo) return KC_OK;
     if (n >= (1ull << 32)) return kc_fail(KC_EINVAL, "radix sort of %zu keys exceeds 2^32", n);
     const uint32_t nblocks = (uint32_t)((n + RS_TILE - 1) / RS_TILE);
@@ -255,6 +264,7 @@ kc_status kc_radix_sort_u64(uint64_t *keys, uint64_t *tmp, size_t n, int bit_lo,
         src = dst;
         dst = t;
     }
-    if (passes & 1) KC_HIP(hipMemcpyAsync(keys, tmp, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    if (sorted) *sorted = src;
+    else if (passes & 1) KC_HIP(hipMemcpyAsync(keys, tmp, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
     return KC_OK;
 }
