@@ -155,6 +155,7 @@ struct CountParams {
     uint64_t *lrows;
     uint64_t *wbits;
     uint32_t *wedges;           // staging: edges of each workgroup-tier G+(u), by rank (optional)
+    unsigned long long *slots;  // 32 partial totals of a single-graph count (summed into *total)
     const uint64_t *woff;
 };
 
@@ -169,9 +170,12 @@ constexpr uint32_t QCTR_FLAG = 32;
 
 // Next chunk start of a queue for the calling wave (all 64 lanes call it), or
 // 0xFFFFFFFF once every counter is spent.  The wave starts at its home counter;
-// `dead` holds the counters it has seen spent.  Each pass either returns or adds
-// a counter to `dead`, so it ends within QCTR passes.  A stale flag costs one
-// atomic, never a wrong chunk.
+// `dead` holds the counters it has seen spent.  Once the home counter is spent,
+// the others are first read (flags and values, one lane each, past the compute
+// unit's cache) and only a live one is taken with an atomic: at the end of a
+// queue the whole grid looks for work at once, and device-scope atomics on a
+// few addresses serialise.  Each pass either returns or adds a counter to
+// `dead`, so it ends within QCTR passes.
 __device__ __forceinline__ uint32_t next_chunk(uint32_t *ctr, uint32_t count, uint32_t chunk, uint32_t home,
                                                uint32_t &dead) {
     const uint32_t lane = kc_lane();
@@ -182,14 +186,21 @@ __device__ __forceinline__ uint32_t next_chunk(uint32_t *ctr, uint32_t count, ui
             if (lane == 0) {
                 const uint64_t c = (uint64_t)atomicAdd(ctr + x * QCTR_STRIDE, 1u) * QCTR + x;
                 if (c * chunk < count) b = (uint32_t)(c * chunk);
-                else ctr[x * QCTR_STRIDE + QCTR_FLAG] = 1u;
+                else __hip_atomic_store(ctr + x * QCTR_STRIDE + QCTR_FLAG, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             b = __shfl(b, 0, 64);
             if (b != 0xFFFFFFFFu) return b;
             dead |= 1u << x;
         }
-        const bool live = lane < QCTR && !((dead >> lane) & 1u) && ctr[lane * QCTR_STRIDE + QCTR_FLAG] == 0u;
+        bool live = false;
+        if (lane < QCTR && !((dead >> lane) & 1u)) {
+            const uint32_t f = __hip_atomic_load(ctr + lane * QCTR_STRIDE + QCTR_FLAG, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t v = __hip_atomic_load(ctr + lane * QCTR_STRIDE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            live = f == 0u && ((uint64_t)v * QCTR + lane) * chunk < count;  // counters only grow
+        }
         const uint64_t lm = __ballot(live);
+        dead |= ~(uint32_t)lm;  // a counter seen spent stays spent
         if (!lm) return 0xFFFFFFFFu;
         const uint64_t after = lm & ~((2ull << x) - 1ull);  // live counters past x
         x = (uint32_t)__builtin_ctzll(after ? after : lm);
@@ -202,11 +213,14 @@ __device__ __forceinline__ uint32_t queue_chunk(uint32_t count, uint32_t workers
     return c < 1u ? 1u : (c > 64u ? 64u : c);
 }
 
-// add a (graph's) partial sum to its total, carry-checked
-__device__ __forceinline__ void add_to(const CountParams &p, uint32_t gid, uint64_t v, int ovf) {
+// add a (graph's) partial sum to its total, carry-checked.  A single graph's total
+// is spread over 32 slots (by the caller's `spread`, e.g. its block), summed by
+// k_total_slots: device-scope atomics on one address serialise when the whole
+// grid finishes at once.
+__device__ __forceinline__ void add_to(const CountParams &p, uint32_t gid, uint64_t v, int ovf, uint32_t spread = 0) {
     if (ovf) atomicOr(p.overflow, 1u);
     if (v == 0) return;
-    unsigned long long *dst = p.gtotals ? p.gtotals + gid : p.total;
+    unsigned long long *dst = p.gtotals ? p.gtotals + gid : p.slots + (spread & 31u);
     const unsigned long long old = atomicAdd(dst, (unsigned long long)v);
     if (old + v < old) atomicOr(p.overflow, 1u);
 }
@@ -672,7 +686,7 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
         if (pg != cur_g) {
             const uint64_t part = kc_wave_sum_checked(acc, &ovf);
             acc = 0;
-            if (lane == 0) add_to(p, cur_g, part, ovf);
+            if (lane == 0) add_to(p, cur_g, part, ovf, blockIdx.x * WAVES + wave);
             cur_g = pg;
         }
         // the pack is a run of the chunk that stays in graph pg
@@ -865,7 +879,7 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
     if (lane == 0) {
         const uint64_t nt = wave_total + rest;
         if (nt < wave_total) ovf = 1;
-        add_to(p, cur_g, nt, ovf);
+        add_to(p, cur_g, nt, ovf, blockIdx.x * WAVES + wave);
     }
 }
 
@@ -1510,7 +1524,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
             }
             const uint32_t gq = p.graph_of ? p.graph_of[u] : 0u;
             if (gq != cur_g) {
-                add_to(p, cur_g, block_total, ovf);
+                add_to(p, cur_g, block_total, ovf, blockIdx.x);
                 block_total = 0;
                 cur_g = gq;
             }
@@ -1520,7 +1534,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
         }
         __syncthreads();
     }
-    if (tid == 0) add_to(p, cur_g, block_total, ovf);
+    if (tid == 0) add_to(p, cur_g, block_total, ovf, blockIdx.x);
 }
 
 // ----------------------------------------------------------------------------
@@ -1572,6 +1586,13 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
             const WgLayout L = wg_layout(dmax < 65 ? 65 : dmax, K);
             const size_t per_block = L.bytes + wg_static_lds(K) + 256;
             uint32_t per_cu = (uint32_t)(di.lds_max / per_block);
+            // and no more than are resident at once (registers): a block launched past
+            // that starts only when the queue is spent
+            int occ = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)&k_count_wg<K, false, MODE>, WG,
+                                                             L.bytes) == hipSuccess &&
+                occ > 0 && (uint32_t)occ < per_cu)
+                per_cu = (uint32_t)occ;
             if (per_cu < 1) per_cu = 1;
             if (per_cu > 8) per_cu = 8;
             if (tu.wg_blocks_per_cu > 0 && (uint32_t)tu.wg_blocks_per_cu < per_cu)
@@ -1625,7 +1646,13 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
         p.count = q.count[0];
         p.next = cursors + 0;
         uint32_t blocks = (q.count[0] + WAVES - 1) / WAVES;
-        const uint32_t cap = (uint32_t)di.cus * (uint32_t)(tu.wave_blocks_per_cu > 0 ? tu.wave_blocks_per_cu : 8);
+        uint32_t per_cu = (uint32_t)(tu.wave_blocks_per_cu > 0 ? tu.wave_blocks_per_cu : 8);
+        int occ = 0;  // resident blocks per CU (registers, LDS)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)&k_count_wave<K, MODE>, WG, 0) ==
+                hipSuccess &&
+            occ > 0 && (uint32_t)occ < per_cu)
+            per_cu = (uint32_t)occ;
+        const uint32_t cap = (uint32_t)di.cus * per_cu;
         if (blocks > cap) blocks = cap;
         // chunk size follows the work per root: staging (reads every out-list) takes
         // half-size chunks, counts from the cache at k <= 5 (a few cheap passes per
@@ -1642,6 +1669,19 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
 __global__ void k_fill_u64(uint64_t *p, size_t n, uint64_t v) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// *total += the 32 partial totals, carry-checked (one wave)
+__global__ void k_total_slots(uint64_t *res) {
+    const uint32_t lane = threadIdx.x;
+    uint64_t v = lane < 32 ? res[KC_RES_SLOTS + lane] : 0ull;
+    int ovf = 0;
+    v = kc_wave_sum_checked(v, &ovf);
+    if (lane == 0) {
+        const uint64_t t = res[0] + v;
+        if (t < v || ovf) res[1] = 1ull;
+        res[0] = t;
+    }
 }
 
 // cache words of each root: its packed bitmap when it is above the wave tier
@@ -1817,6 +1857,7 @@ kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_a
     p.rank2id = g->rank2id;
     p.per_root = a.per_root;
     p.total = (unsigned long long *)res;
+    p.slots = (unsigned long long *)(res + KC_RES_SLOTS);
     p.overflow = (uint32_t *)(res + 1);
     p.colored = a.colored;
     p.scheme = a.scheme;
@@ -1856,6 +1897,7 @@ kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_a
         default:
             return kc_fail(KC_EINVAL, "k=%d outside the counting kernels' range", a.k);
     }
+    if (!gtotals) hipLaunchKernelGGL(k_total_slots, dim3(1), dim3(64), 0, s, res);
     KC_HIP(hipGetLastError());
     return KC_OK;
 }

@@ -198,7 +198,13 @@ kc_status degrees(const uint64_t *ukeys, size_t M, int B, uint64_t mask, uint32_
     const int RB = B - 8 * p > 0 ? B - 8 * p : 0;
     const uint64_t *by = ukeys;
     kc_tmp copy, tmp;
-    if (RB < B) {
+    if (RB < B && p == 1) {
+        // one pass reads ukeys and writes tmp only: no copy needed
+        KC_TRY(kc_tmp_alloc(tmp, M * 8, s));
+        uint64_t *sorted = nullptr;
+        KC_TRY(kc_radix_sort_u64(const_cast<uint64_t *>(ukeys), tmp.as<uint64_t>(), M, RB, B, s, &sorted));
+        by = sorted;
+    } else if (RB < B) {
         KC_TRY(kc_tmp_alloc(copy, M * 8, s));
         KC_TRY(kc_tmp_alloc(tmp, M * 8, s));
         KC_HIP(hipMemcpyAsync(copy.p, ukeys, M * 8, hipMemcpyDeviceToDevice, s));
@@ -268,8 +274,7 @@ kc_status kc_canonicalise(kc_graph *g, const uint32_t *d_src, const uint32_t *d_
         if (M) KC_TRY(degrees(g->ukeys, M, B, mask, n, g->deg, s));
     }
     g->m = M;
-    KC_TRY(kc_sync(s));
-    return KC_OK;
+    return KC_OK;  // the caller synchronises
 }
 
 // The symmetric CSR (rowptr, col) of the simple graph, built on first request.

@@ -180,7 +180,8 @@ const kc_tuning_t &kc_tuning_now();
 
 // Scheduler (kc_sched.hip)
 #define KC_WG_CLASSES 16
-#define KC_RES_WORDS 1040  // per-count result block: total, overflow flag, then u32 queue counters
+#define KC_RES_WORDS 1072  // per-count result block: total, overflow flag, u32 queue counters, total slots
+#define KC_RES_SLOTS 1040  // first of the 32 partial-total words (summed into word 0 at the end)
 #define KC_MLP_IN 8
 #define KC_MLP_H 32
 #define KC_MLP_PARAMS (KC_MLP_IN * KC_MLP_H + KC_MLP_H + KC_MLP_H * KC_MLP_H + KC_MLP_H + KC_MLP_H + 1)

@@ -142,10 +142,11 @@ __global__ void k_degree_parts(const uint32_t *q, uint32_t cnt, const uint64_t *
 
 // Work items of the workgroup tier (staged handles), three grid passes and no
 // host round trip:
-//   1. the sum of the roots' edge counts of G+(u) (kept when staging);
-//   2. items per root, ceil(edges / target) with target the smaller of four times
+//   1. the sum of the roots' estimated work (root_est, from the edges of G+(u)
+//      kept when staging);
+//   2. items per root, ceil(est / target) with target the smaller of four times
 //      the mean and 1/1024 of the total (at least 1), at most min(64, out-degree);
-//      items per 8-bit edge bucket;
+//      items per 8-bit estimate bucket;
 //   3. items written bucket by bucket, heaviest bucket first (a counting sort:
 //      longest-processing-time order at bucket resolution), the list padded to
 //      its bound with skipped items.
@@ -165,9 +166,22 @@ __global__ void k_wq_clear(WqAux *a) {
     }
 }
 
-__global__ void k_edge_sum(const uint32_t *q, uint32_t cnt, const uint32_t *wedges, WqAux *a) {
+// Estimated work of a root from the edges c and nodes d of G+(u): c^1.5 / d^2
+// (time grows with the size and the density of G+(u)), in 1/64 units, saturated.
+__device__ __forceinline__ uint32_t root_est(uint32_t c, uint64_t d) {
+    const double dd = d ? (double)d : 1.0;
+    const double e = 64.0 * (double)c * sqrt((double)c) / (dd * dd);
+    return e >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)e;
+}
+__device__ __forceinline__ uint32_t est_of(const uint32_t *q, size_t i, const uint32_t *wedges, const uint64_t *optr) {
+    const uint32_t u = q[i];
+    return root_est(wedges[u], optr[u + 1] - optr[u]);
+}
+
+__global__ void k_edge_sum(const uint32_t *q, uint32_t cnt, const uint32_t *wedges, const uint64_t *optr,
+                           WqAux *a) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint64_t c = i < cnt ? wedges[q[i]] : 0u;
+    uint64_t c = i < cnt ? est_of(q, i, wedges, optr) : 0u;
     for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
     if ((threadIdx.x & 63u) == 0 && c) atomicAdd(&a->sum, (double)c);
 }
@@ -192,7 +206,7 @@ __global__ void k_root_parts(const uint32_t *q, const uint32_t *wedges, uint32_t
     if (target < 1.0) target = 1.0;
     const uint32_t u = q[i];
     const uint64_t d = optr[u + 1] - optr[u];
-    const uint32_t c = wedges[u];
+    const uint32_t c = root_est(wedges[u], d);
     double np = ceil((double)c / target);
     const double cap = d < 64 ? (double)(d ? d : 1) : 64.0;
     np = np < 1.0 ? 1.0 : (np > cap ? cap : np);
@@ -202,8 +216,8 @@ __global__ void k_root_parts(const uint32_t *q, const uint32_t *wedges, uint32_t
 
 constexpr uint32_t WQ_SKIP = 0xFFFFFFFFu;
 
-__global__ void k_emit_items(const uint32_t *q, const uint32_t *wedges, const uint32_t *parts, uint32_t cnt,
-                             WqAux *a, uint32_t bound, uint64_t *items) {
+__global__ void k_emit_items(const uint32_t *q, const uint32_t *wedges, const uint64_t *optr, const uint32_t *parts,
+                             uint32_t cnt, WqAux *a, uint32_t bound, uint64_t *items) {
     __shared__ uint32_t base[256];
     __shared__ uint32_t s_total;
     const uint32_t tid = threadIdx.x;
@@ -222,7 +236,7 @@ __global__ void k_emit_items(const uint32_t *q, const uint32_t *wedges, const ui
     __syncthreads();
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + tid; i < cnt; i += stride) {
-        const uint32_t u = q[i], b = edge_bucket(wedges[u]), np = parts[i];
+        const uint32_t u = q[i], b = edge_bucket(est_of(q, i, wedges, optr)), np = parts[i];
         const uint32_t off = base[b] + atomicAdd(&a->bcur[b], np);
         for (uint32_t pt = 0; pt < np; ++pt)
             if (off + pt < bound) items[off + pt] = ((uint64_t)u << 32) | ((uint64_t)pt << 16) | (uint64_t)np;
@@ -251,11 +265,12 @@ kc_status build_work_items(kc_graph *g, uint32_t first, uint32_t cnt) {
     KC_TRY(kc_dev_alloc((void **)&g->wq, (size_t)bound * 8, s));
     WqAux *a = aux.as<WqAux>();
     hipLaunchKernelGGL(k_wq_clear, dim3(1), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_edge_sum, dim3(grid_for(cnt)), dim3(T), 0, s, q, cnt, (const uint32_t *)g->wedges, a);
+    hipLaunchKernelGGL(k_edge_sum, dim3(grid_for(cnt)), dim3(T), 0, s, q, cnt, (const uint32_t *)g->wedges,
+                       (const uint64_t *)g->optr, a);
     hipLaunchKernelGGL(k_root_parts, dim3(grid_for(cnt)), dim3(T), 0, s, q, (const uint32_t *)g->wedges, cnt,
                        (const uint64_t *)g->optr, a, parts.as<uint32_t>());
     hipLaunchKernelGGL(k_emit_items, dim3(grid_for(bound)), dim3(T), 0, s, q, (const uint32_t *)g->wedges,
-                       (const uint32_t *)parts.as<uint32_t>(), cnt, a, bound, g->wq);
+                       (const uint64_t *)g->optr, (const uint32_t *)parts.as<uint32_t>(), cnt, a, bound, g->wq);
     KC_HIP(hipGetLastError());
     g->wq_count = bound;
     g->wq_first = first;
