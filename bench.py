@@ -241,9 +241,8 @@ def bench_batch(args, K, torch, stream):
     with torch.cuda.stream(bs):
         hs = [_device_graph(K, torch, el, bs.cuda_stream) for el in els]
         log("batch: autotuning")
-        cache = os.path.join(ROOT, "gpurun_out", "kc_tune.tsv") if os.path.isdir(os.path.join(ROOT, "gpurun_out")) \
-            else None
-        tuning = K.kc_autotune(hs, k, cache)
+        # optional autotune cache file (KC_TUNE_CACHE); without it every run tunes afresh
+        tuning = K.kc_autotune(hs, k, os.environ.get("KC_TUNE_CACHE") or None)
         t0 = time.perf_counter()
         per_graph = [K.kc_count(h, k) for h in hs]
         t1 = time.perf_counter()

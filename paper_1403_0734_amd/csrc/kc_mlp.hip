@@ -5,7 +5,7 @@
 // The paper shows the reduce-3 instances are heavily skewed and that the slow
 // ones should be spread over more workers (Sections 5 and 7).  The prediction
 // orders the queue heaviest first and moves small but dense roots to the
-// workgroup tier; the degree order is the fallback and the judge.
+// workgroup tier; the degree order is the fallback and the yardstick.
 //
 // Features of root u (rank space), for clique size k:
 //   0 log1p d+(u)            1 log1p sum_{x in Gamma+(u)} d+(x)  (wedges)
