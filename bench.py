@@ -59,7 +59,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the counting path has no multi-GPU mode in this build "
+        print("bench.py measures one GPU only: the counting path has no multi-GPU mode "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
