@@ -106,12 +106,16 @@ def batch_graphs():
     return gs
 
 
+@pytest.mark.parametrize("cache", ["1", "0"])
 @pytest.mark.parametrize("k", [3, 5, 6])
-def test_batch_matches_per_graph(stream, k):
+def test_batch_matches_per_graph(stream, k, cache, monkeypatch):
+    """Batched counts equal per-graph counts: with the plan's union staged once and
+    the from-cache kernels captured (default), and staged on every replay."""
+    monkeypatch.setenv("KC_STAGE_CACHE", cache)
     els = batch_graphs()
     want = [O.OracleGraph.from_edgelist(el).count(k) for el in els]
     hs = [graph_on(el, stream) for el in els]
-    announce(f"batch k={k}")
+    announce(f"batch k={k} cache={cache}")
     for rep in range(3):  # eager + capture, then graph replays
         assert K.kc_count_batch(hs, k) == want, rep
     assert [K.kc_count(h, k) for h in hs] == want
