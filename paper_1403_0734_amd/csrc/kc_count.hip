@@ -360,10 +360,22 @@ __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int el
             } else if (R == 2) {
                 acc += edges_inside(P, A.rows);
             } else {
+                // four members per step as in edges_inside: their row reads in flight together
                 while (P) {
-                    const uint32_t v = (uint32_t)__builtin_ctzll(P);
+                    const uint32_t v0 = (uint32_t)__builtin_ctzll(P);
                     P &= P - 1;
-                    acc += edges_inside(P & A.rows[v], A.rows);
+                    const uint64_t P1 = P;
+                    const uint32_t v1 = P ? (uint32_t)__builtin_ctzll(P) : 0u;
+                    P &= P - 1;
+                    const uint64_t P2 = P;
+                    const uint32_t v2 = P ? (uint32_t)__builtin_ctzll(P) : 0u;
+                    P &= P - 1;
+                    const uint64_t P3 = P;
+                    const uint32_t v3 = P ? (uint32_t)__builtin_ctzll(P) : 0u;
+                    P &= P - 1;
+                    const uint64_t r0 = A.rows[v0], r1 = A.rows[v1], r2 = A.rows[v2], r3 = A.rows[v3];
+                    acc += edges_inside(P1 & r0, A.rows) + edges_inside(P2 & r1, A.rows) +
+                           edges_inside(P3 & r2, A.rows) + edges_inside(P & r3, A.rows);
                 }
             }
         }
