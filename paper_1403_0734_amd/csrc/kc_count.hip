@@ -867,7 +867,11 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
         if (MODE == MODE_STORE) {
             // keep the staged rows (root-local bit positions) for later counts
             wave_sync();
-            if (lane < d) p.lrows[rbase + (lane - r0)] = sm.A.rows[lane] >> r0;
+            if (lane < d) {
+                const uint64_t row = sm.A.rows[lane] >> r0;
+                p.lrows[rbase + (lane - r0)] = row;
+                acc += (uint64_t)__popcll(row);  // the root's triangles (q_3), for free
+            }
             wave_sync();
             continue;
         }
@@ -1296,15 +1300,18 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                 dst[w] = bm[w];
                 ec += (uint32_t)__popcll(bm[w]);
             }
-            if (p.wedges) {  // the edge count orders later counts' work (heaviest first)
-                ec = kc_wave_sum_u32(ec);
-                if (lane == 0) s_red[wave] = ec;
-                __syncthreads();
-                if (tid == 0) {
-                    uint64_t e = 0;
-                    for (int w = 0; w < WAVES; ++w) e += s_red[w];
-                    p.wedges[u] = e > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)e;
-                }
+            // the edges of G+(u) are its triangles (q_3 at u, added to the total) and
+            // order later counts' work (heaviest first)
+            ec = kc_wave_sum_u32(ec);
+            if (lane == 0) s_red[wave] = ec;
+            __syncthreads();
+            if (tid == 0) {
+                uint64_t e = 0;
+                for (int w = 0; w < WAVES; ++w) e += s_red[w];
+                if (p.wedges) p.wedges[u] = e > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)e;
+                const uint64_t nt = block_total + e;
+                if (nt < block_total) ovf = 1;
+                block_total = nt;
             }
             __syncthreads();
             continue;
@@ -1884,8 +1891,10 @@ kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_a
     p.wedges = g->wedges;
     uint32_t *cursors = (uint32_t *)(res + 2);
     if (a.store) {
-        // staging into the cache does not depend on k
+        // staging into the cache does not depend on k; its total is q_3 (the edges of
+        // every G+(u)), kept in res as a count would leave it
         launch_tiers<3, MODE_STORE>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev);
+        if (!gtotals) hipLaunchKernelGGL(k_total_slots, dim3(1), dim3(64), 0, s, res);
         KC_HIP(hipGetLastError());
         return KC_OK;
     }
@@ -1923,12 +1932,32 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
     // schedule); later counts read it (KC_STAGE_CACHE=0 stages per call instead)
     kc_count_args ac = a;
     const char *sc = getenv("KC_STAGE_CACHE");
+    bool staged_now = false;
     if (!(sc && sc[0] == '0')) {
         int wd = kc_tuning_now().wave_dmax;
         wd = wd < 1 ? 1 : (wd > 64 ? 64 : wd);
         kc_graph *gm = const_cast<kc_graph *>(g);
+        const int before = gm->staged;
         KC_TRY(kc_stage(gm, wd));
         ac.cached = gm->staged == 1;
+        staged_now = before != 1 && gm->staged == 1;
+    }
+    if (staged_now && a.k == 3 && !a.colored && !a.per_root && !getenv("KC_TEST_TOTAL_BIAS")) {
+        // the staging pass just left q_3 in the result block
+        for (int e = 1; e < 6; ++e) KC_HIP(hipEventRecord(g->ev[e], s));
+        uint64_t *h_res = kc_pinned_scratch();
+        KC_HIP(hipMemcpyAsync(h_res, g->d_res, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        KC_TRY(kc_sync(s));
+        float t_sched = 0.f;
+        (void)hipEventElapsedTime(&t_sched, g->ev[0], g->ev[1]);
+        kc_graph *gm = const_cast<kc_graph *>(g);
+        for (int t = 0; t < 3; ++t) gm->t_tier[t] = 0.f;
+        gm->t_schedule = t_sched;
+        gm->t_count = 0.f;
+        gm->t_total = t_sched;
+        *total = h_res[0];
+        *overflow = h_res[1] != 0;
+        return KC_OK;
     }
     kc_queue q;
     KC_TRY(kc_build_queue(g, a.k, a.policy, dcap, q));
