@@ -56,17 +56,24 @@ __device__ __forceinline__ size_t lower_bound_key(const uint64_t *keys, size_t m
     return lo;
 }
 
-// deg[x] = number of edges with smaller end x
+// deg[x] = number of edges with smaller end x: the run of keys from x's first to
+// x+1's first.  One search per node: the start of x's run is the lane below's end
+// (lane 0 searches it too).
 __global__ void k_deg_low_end(const uint64_t *ukeys, size_t m, int B, uint32_t n, uint32_t *deg) {
     const size_t x = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= n) return;
-    const size_t a = lower_bound_key(ukeys, m, (uint64_t)x, ~0ull, B);
-    const size_t b = lower_bound_key(ukeys, m, (uint64_t)x + 1, ~0ull, B);
-    deg[x] = (uint32_t)(b - a);
+    const uint32_t lane = threadIdx.x & 63u;
+    const size_t b = x < n ? lower_bound_key(ukeys, m, (uint64_t)x + 1, ~0ull, B) : 0;
+    const unsigned long long below = __shfl_up((unsigned long long)b, 1, 64);
+    size_t a = (size_t)below;
+    if (lane == 0 && x < n) a = lower_bound_key(ukeys, m, (uint64_t)x, ~0ull, B);
+    if (x < n) deg[x] = (uint32_t)(b - a);
 }
 
-// deg[x] += number of edges with larger end x, for the range of block blockIdx.x
-__global__ void __launch_bounds__(256) k_deg_high_end(const uint64_t *bykeys, size_t m, uint64_t mask, int RB,
+// deg[x] += number of edges with larger end x, for the range of block blockIdx.x.
+// One block per range (2^RB nodes, as few as 256 blocks): 1024 threads, so that
+// enough loads are in flight on each compute unit.
+constexpr unsigned DEG_HIGH_THREADS = 1024;
+__global__ void __launch_bounds__(DEG_HIGH_THREADS) k_deg_high_end(const uint64_t *bykeys, size_t m, uint64_t mask, int RB,
                                                       uint32_t n, uint32_t *deg) {
     extern __shared__ uint32_t cnt[];
     const uint32_t range = 1u << RB;
@@ -214,7 +221,8 @@ kc_status degrees(const uint64_t *ukeys, size_t M, int B, uint64_t mask, uint32_
     const uint64_t ranges = (((uint64_t)n - 1) >> RB) + 1;
     const size_t lds = (size_t)4 << RB;
     (void)hipFuncSetAttribute((const void *)&k_deg_high_end, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_deg_high_end, dim3((unsigned)ranges), dim3(256), lds, s, by, M, mask, RB, n, deg);
+    hipLaunchKernelGGL(k_deg_high_end, dim3((unsigned)ranges), dim3(DEG_HIGH_THREADS), lds, s, by, M, mask, RB, n,
+                       deg);
     KC_HIP(hipGetLastError());
     return KC_OK;
 }
