@@ -113,9 +113,14 @@ kc_status kc_count_per_root(const kc_graph *g, int32_t k, uint64_t *dev_counts, 
 /* Exact q_k (3 <= k <= KC_KMAX) of num graphs at once; q_out[i] is the count of gs[i].
  * The graphs are laid side by side on the device as one disjoint union and counted
  * by the persistent tier kernels from one work queue (ordered by tier, graph and
- * out-degree); the count launches are captured in a HIP graph that is replayed when
- * the same graphs (same handles) are counted again at the same k.  Every graph must
- * be oriented, on the same device and bound to the same stream; num <= 65536. */
+ * out-degree).  The plan built on the first call stages every G+(u) of the union
+ * once (device memory of about 8 bytes per edge plus the larger roots' bitmaps,
+ * held until a different batch is planned or one of its handles is destroyed; not
+ * kept, and staged on every replay, when it would take more than half the free
+ * device memory), and captures the from-cache count launches in a HIP graph that is
+ * replayed when the same graphs (same handles) are counted again at the same k.
+ * Every graph must be oriented, on the same device and bound to the same stream;
+ * num <= 65536. */
 kc_status kc_count_batch(kc_graph *const *gs, uint32_t num, int32_t k, uint64_t *q_out);
 
 /* Scheduling policy for later counts.  For KC_SCHED_LEARNED, weights_path names a
