@@ -90,8 +90,12 @@ kc_status kc_graph_create(const uint32_t *src, const uint32_t *dst, uint64_t m_i
 kc_status kc_orient(kc_graph *g);
 
 /* Exact q_k (Section 3, Theorem 1) for 1 <= k <= KC_KMAX: q_1 = n, q_2 = m, and for
- * k >= 3 the sum over u of the (k-1)-cliques of G+(u).  KC_ESTATE if not oriented;
- * KC_EOVERFLOW if q_k >= 2^64. */
+ * k >= 3 the sum over u of the (k-1)-cliques of G+(u).  The first count on a handle
+ * stages every G+(u) into a device cache kept by the handle (about 8 bytes per edge
+ * plus the bitmaps of roots above the one-wave limit; not kept when it would take
+ * more than half the free device memory, or with KC_STAGE_CACHE=0); later counts of
+ * any k and either colouring read it.  The staging pass itself yields q_3.
+ * KC_ESTATE if not oriented; KC_EOVERFLOW if q_k >= 2^64. */
 kc_status kc_count(const kc_graph *g, int32_t k, uint64_t *q_out);
 
 /* Colour-sampled estimate (Section 6, cFFF_k) for 3 <= k <= KC_KMAX and c >= 1.
