@@ -70,6 +70,9 @@ def _load():
             "kco_count_colored_root": (i32, [P, u32, i32, u32, u64, i32, P]),
             "kco_count_colored_per_root": (i32, [P, i32, u32, u64, i32, i32, P]),
             "kco_count_colored": (i32, [P, i32, u32, u64, i32, i32, P]),
+            "kco_hash_pair": (u64, [u64, u32, u32, u32]),
+            "kco_count_pair_sampled_root": (i32, [P, u32, i32, u64, u64, P]),
+            "kco_count_pair_sampled": (i32, [P, i32, u64, u64, i32, P]),
             "kco_work_root": (i32, [P, u32, i32, P, P]),
             "kco_work_per_root": (i32, [P, i32, i32, P, P]),
         }
@@ -104,6 +107,19 @@ def hash_node(seed: int, x: int) -> int:
 
 def color(h: int, c: int) -> int:
     return int(_load().kco_color(h, c))
+
+
+def hash_pair(seed: int, u: int, x: int, y: int) -> int:
+    """Pair-sampling hash of the pair (x, y) of Gamma+(u), x before y in the order."""
+    return int(_load().kco_hash_pair(seed, u, x, y))
+
+
+def pair_threshold(p: float) -> int:
+    """t = floor(p * 2^32): a pair is kept iff (hash >> 32) < t (Section 6, plain pair
+    sampling; t = 2^32 keeps every pair)."""
+    if not (0.0 < p <= 1.0):
+        raise ValueError("p must be in (0, 1]")
+    return min(int(p * 2**32), 2**32)
 
 
 class OracleGraph:
@@ -205,6 +221,19 @@ class OracleGraph:
     def count_colored_root(self, u: int, k: int, c: int, seed: int, scheme: int = COLOR_PER_ROOT) -> int:
         q = np.zeros(1, np.uint64)
         _check(_load().kco_count_colored_root(self._h, u, k, c, seed, scheme, _p(q)), "count_colored_root")
+        return int(q[0])
+
+    def count_pair_sampled(self, k: int, p: float, seed: int, threads: int = 0) -> int:
+        """Raw plain-pair-sampled count: the (k-1)-cliques of every sampled G+(u)."""
+        q = np.zeros(1, np.uint64)
+        _check(_load().kco_count_pair_sampled(self._h, k, pair_threshold(p), seed, threads, _p(q)),
+               "count_pair_sampled")
+        return int(q[0])
+
+    def count_pair_sampled_root(self, u: int, k: int, p: float, seed: int) -> int:
+        q = np.zeros(1, np.uint64)
+        _check(_load().kco_count_pair_sampled_root(self._h, u, k, pair_threshold(p), seed, _p(q)),
+               "count_pair_sampled_root")
         return int(q[0])
 
     def work_root(self, u: int, k: int):

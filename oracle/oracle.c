@@ -367,6 +367,94 @@ int kco_count_colored(const kco_graph *g, int k, uint32_t c, uint64_t seed, int 
 }
 
 /* ------------------------------------------------------------------------- */
+/* Plain pair sampling FFF_k(p) (Section 6, plain pair sampling): every pair of
+ * high-neighbours of u that is an edge of G+(u) is kept independently with
+ * probability p, and the root contributes the (k-1)-cliques of the sampled G+(u);
+ * a k-clique survives when all C(k-1, 2) pairs of its non-minimum nodes do.
+ * Randomness (the paper leaves it unspecified): the pair (x, y), x before y in the
+ * order, is kept iff (H2 >> 32) < t, with H2 = mix64(H(seed, u, x) ^ mix64(y)) and
+ * t = floor(p * 2^32) (t = 2^32 keeps every pair). */
+uint64_t kco_hash_pair(uint64_t seed, uint32_t u, uint32_t x, uint32_t y) {
+    return kco_mix64(kco_hash_root(seed, u, x) ^ kco_mix64((uint64_t)y));
+}
+
+/* l-cliques inside the local node list P (ascending local indices) of a graph
+ * given by its upper adjacency matrix adj[i * d + j] (i < j). */
+static int pcnt(const uint8_t *adj, uint64_t d, const uint32_t *P, uint64_t np, int l, uint32_t *buf,
+                uint64_t *out) {
+    if (l <= 0) { *out = 1; return KCO_OK; }
+    if (l == 1) { *out = np; return KCO_OK; }
+    uint64_t total = 0;
+    for (uint64_t a = 0; a < np; ++a) {
+        uint64_t nq = 0;
+        for (uint64_t b = a + 1; b < np; ++b)
+            if (adj[(uint64_t)P[a] * d + P[b]]) buf[nq++] = P[b];
+        uint64_t sub;
+        int st = pcnt(adj, d, buf, nq, l - 1, buf + np, &sub);
+        if (st) return st;
+        if (__builtin_add_overflow(total, sub, &total)) return KCO_EOVERFLOW;
+    }
+    *out = total;
+    return KCO_OK;
+}
+
+int kco_count_pair_sampled_root(const kco_graph *g, uint32_t u, int k, uint64_t t, uint64_t seed, uint64_t *out) {
+    if (!g || !out || u >= g->n || k < 3) return KCO_EINVAL;
+    const uint32_t *N = g->hn + g->hp[u];
+    const uint64_t d = g->hp[u + 1] - g->hp[u];
+    if (d < (uint64_t)(k - 1)) { *out = 0; return KCO_OK; }
+    uint8_t *adj = (uint8_t *)calloc(d * d, 1);
+    uint32_t *P = (uint32_t *)malloc(sizeof(uint32_t) * (d * (uint64_t)k + 1));
+    if (!adj || !P) { free(adj); free(P); return KCO_ENOMEM; }
+    for (uint64_t i = 0; i < d; ++i) {
+        /* members of Gamma+(N[i]) that are later members of Gamma+(u): a merge by key */
+        const uint32_t *M = g->hn + g->hp[N[i]];
+        const uint64_t mm = g->hp[N[i] + 1] - g->hp[N[i]];
+        uint64_t a = i + 1, b = 0;
+        while (a < d && b < mm) {
+            const uint64_t ka = key_of(g, N[a]), kb = key_of(g, M[b]);
+            if (ka < kb) ++a;
+            else if (kb < ka) ++b;
+            else {
+                if ((kco_hash_pair(seed, u, N[i], N[a]) >> 32) < t) adj[i * d + a] = 1;
+                ++a;
+                ++b;
+            }
+        }
+    }
+    for (uint64_t i = 0; i < d; ++i) P[i] = (uint32_t)i;
+    int st = pcnt(adj, d, P, d, k - 1, P + d, out);
+    free(adj);
+    free(P);
+    return st;
+}
+
+int kco_count_pair_sampled(const kco_graph *g, int k, uint64_t t, uint64_t seed, int threads, uint64_t *raw) {
+    if (!g || !raw || k < 3) return KCO_EINVAL;
+    uint64_t *cc = (uint64_t *)malloc(sizeof(uint64_t) * (g->n ? g->n : 1));
+    if (!cc) return KCO_ENOMEM;
+    int status = KCO_OK;
+#ifdef _OPENMP
+    if (threads <= 0) threads = omp_get_max_threads();
+    #pragma omp parallel for schedule(dynamic, 16) num_threads(threads)
+#endif
+    for (int64_t x = 0; x < (int64_t)g->n; ++x) {
+        int st = kco_count_pair_sampled_root(g, (uint32_t)x, k, t, seed, &cc[x]);
+        if (st) {
+            #pragma omp critical
+            status = st;
+        }
+    }
+    (void)threads;
+    uint64_t total = 0;
+    for (uint32_t x = 0; status == KCO_OK && x < g->n; ++x)
+        if (__builtin_add_overflow(total, cc[x], &total)) status = KCO_EOVERFLOW;
+    free(cc);
+    if (status == KCO_OK) *raw = total;
+    return status;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Per-root work.  Running cnt(Gamma+(u), k-1) performs one intersection for
  * every l-clique of G+(u) with 1 <= l <= k-2 (the clique's last node v is the
  * node whose neighbourhood is intersected).  `inter` counts them.  `words`

@@ -287,6 +287,56 @@ def test_colour_estimator_unbiased(scheme):
     assert abs(est.mean() - q) < 5 * se + 1e-9, (est.mean(), q, se)
 
 
+# ---------------------------------------------------------------- pair sampling
+@pytest.mark.parametrize("el", [S.complete(9), S.random_graph(40, 0.5, 71), S.turan(24, 5),
+                                S.complete_multipartite([3, 4, 5, 2])], ids=lambda e: e.name[:30])
+def test_pair_sampling_p_one_is_exact(el):
+    """p = 1 keeps every pair: the sampled local graphs are the G+(u) themselves, so
+    the raw count is q_k (computed by the separate list-merge counter)."""
+    g = og(el)
+    for k in range(3, 7):
+        assert g.count_pair_sampled(k, 1.0, 99) == g.count(k), k
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_pair_sampling_bruteforce(seed):
+    """k-subset form (Section 6, plain pair sampling): a clique S with smallest node
+    u survives when every pair {x, y} of S minus u, x before y in the order, is kept:
+    (hash_pair(seed, u, x, y) >> 32) < floor(p 2^32)."""
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(9, 15))
+    el = S.random_graph(n, 0.8, 90 + seed)
+    g = og(el)
+    E = edge_set(el)
+    for p in [0.3, 0.5, 0.85]:
+        t = O.pair_threshold(p)
+        hseed = int(rng.integers(0, 2**63))
+        for k in range(3, 7):
+            cl, adj = brute_cliques(n, E, k)
+            order = lambda x: (len(adj[x]), x)
+            want = 0
+            for S_ in cl:
+                u = prec_min(S_, adj)
+                rest = sorted((x for x in S_ if x != u), key=order)
+                if all((O.hash_pair(hseed, u, x, y) >> 32) < t for x, y in itertools.combinations(rest, 2)):
+                    want += 1
+            assert g.count_pair_sampled(k, p, hseed) == want, (seed, p, k)
+
+
+def test_pair_sampling_estimator_unbiased():
+    """E[raw / p^C(k-1,2)] = q_k (Section 6: each k-clique survives with probability
+    p^((k-1)(k-2)/2), its C(k-1, 2) pairs below the minimum node kept independently)."""
+    el = S.random_graph(16, 0.75, 12)
+    g = og(el)
+    k, p, trials = 4, 0.6, 3000
+    q = g.count(k)
+    keep = O.pair_threshold(p) / 2**32
+    scale = keep ** -math.comb(k - 1, 2)
+    est = np.array([g.count_pair_sampled(k, p, s) * scale for s in range(trials)], dtype=np.float64)
+    se = est.std(ddof=1) / math.sqrt(trials)
+    assert abs(est.mean() - q) < 5 * se + 1e-9, (est.mean(), q, se)
+
+
 # ---------------------------------------------------------------- work labels
 @pytest.mark.parametrize("seed", range(4))
 def test_work_counts_cliques_of_high_neighbourhood(seed):
