@@ -160,6 +160,17 @@ def main():
     optr = torch.zeros(n + 1, dtype=torch.int64, device=dev)
     r2i = torch.zeros(n, dtype=torch.int32, device=dev)
     K.kc_get_oriented(h, optr.data_ptr(), None, r2i.data_ptr())
+    # plain pair sampling (Section 6) on the same graph, outside the timed steps: the
+    # colour estimate's k with p = 1/c, the same expected share of pairs
+    pk, pp, pseed = ck, 1.0 / cc, 23
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    ps = K.kc_count_pair_sampled(h, pk, pp, pseed)
+    tp1 = time.perf_counter()
+    pair_sampling = {"k": pk, "p": pp, "seed": pseed, "raw": ps.raw, "estimate": ps.estimate, "exact": qs.get(pk),
+                     "rel_error": abs(ps.estimate - qs[pk]) / qs[pk] if qs.get(pk) else None,
+                     "colour_rel_error": abs(est.estimate - qs[ck]) / qs[ck] if qs.get(ck) else None,
+                     "ms_call": (tp1 - tp0) * 1e3, "ms_mask_and_count": K.kc_last_timings(h)[1]}
     K.kc_graph_destroy(h)
     torch.cuda.synchronize()
     d_rank = np.diff(optr.cpu().numpy())
@@ -189,7 +200,7 @@ def main():
                    "ks": ks, "schedule": args.schedule,
                    "colour_estimate": {"k": ck, "c": cc, "seed": cseed, "scheme": "per_root", "raw": est.raw,
                                        "estimate": est.estimate}},
-        "per_k": per_k, "roofline": roofline,
+        "per_k": per_k, "roofline": roofline, "pair_sampling": pair_sampling,
     }
 
     if not args.no_cpu_baseline:

@@ -107,6 +107,17 @@ kc_status kc_count(const kc_graph *g, int32_t k, uint64_t *q_out);
 kc_status kc_count_colored(const kc_graph *g, int32_t k, uint32_t c, uint64_t seed, int32_t scheme,
                            kc_estimate *out);
 
+/* Plain pair-sampled estimate (Section 6, plain pair sampling, FFF_k(p)) for
+ * 3 <= k <= KC_KMAX and 0 < p <= 1: every pair {x, y} of Gamma+(u) joined by an
+ * edge is kept independently per root u; raw = sum over u of the (k-1)-cliques of
+ * the sampled G+(u); estimate = raw / p'^e with e = C(k-1, 2) (scale_exponent) and
+ * p' = t / 2^32 the exact keep probability, t = floor(p 2^32).  The pair (x, y), x
+ * before y in the order, is kept iff (H2 >> 32) < t with
+ *   H2 = mix64(mix64(seed ^ mix64((u << 32) | x)) ^ mix64(y))  (original ids).
+ * estimate_u64 is exact (and set) only for p = 1, where raw == q_k.  Counts a masked
+ * copy of the handle's staged cache: KC_ENOMEM when the cache is not kept. */
+kc_status kc_count_pair_sampled(const kc_graph *g, int32_t k, double p, uint64_t seed, kc_estimate *out);
+
 /* Per-root counts q_{u,k-1} (Section 3: the count the reducer for u emits) into the
  * caller's device array dev_counts[n], indexed by original id; optionally the
  * per-root intersection work into dev_work[n] (may be NULL): the number of

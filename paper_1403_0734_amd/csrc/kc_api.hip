@@ -237,6 +237,36 @@ kc_status kc_count_colored(const kc_graph *g, int32_t k, uint32_t c, uint64_t se
     return KC_OK;
 }
 
+kc_status kc_count_pair_sampled(const kc_graph *g, int32_t k, double p, uint64_t seed, kc_estimate *out) {
+    g_msg[0] = 0;
+    if (!out) return kc_fail(KC_EINVAL, "out is NULL");
+    KC_TRY(check_count(g, k, 3));
+    if (!(p > 0.0 && p <= 1.0)) return kc_fail(KC_EINVAL, "p must be in (0, 1]");
+    const long double scaled = (long double)p * 4294967296.0L;
+    const uint64_t t = scaled >= 4294967296.0L ? (1ull << 32) : (uint64_t)scaled;  // floor(p 2^32)
+    if (t == 0) return kc_fail(KC_EINVAL, "p below 2^-32");
+    kc_count_args a;
+    a.k = k;
+    a.sampled = 1;
+    a.pair_t = t;
+    a.seed = seed;
+    a.policy = g->policy;
+    uint64_t raw = 0;
+    int ovf = 0;
+    KC_TRY(kc_count_impl(g, a, &raw, &ovf));
+    if (ovf) return kc_fail(KC_EOVERFLOW, "raw pair-sampled count >= 2^64");
+    // each k-clique survives with probability (t / 2^32)^e, e = C(k-1, 2)
+    const int e = (k - 1) * (k - 2) / 2;
+    long double est = (long double)raw;
+    for (int i = 0; i < e; ++i) est *= 4294967296.0L / (long double)t;
+    out->raw = raw;
+    out->scale_exponent = e;
+    out->estimate = (double)est;
+    out->estimate_fits_u64 = t == (1ull << 32) ? 1 : 0;  // exact only when every pair is kept
+    out->estimate_u64 = out->estimate_fits_u64 ? raw : 0;
+    return KC_OK;
+}
+
 kc_status kc_graph_info(const kc_graph *g, uint32_t *n, uint64_t *m, uint32_t *max_outdeg) {
     g_msg[0] = 0;
     if (!g) return kc_fail(KC_EINVAL, "graph is NULL");

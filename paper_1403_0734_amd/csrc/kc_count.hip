@@ -1713,6 +1713,68 @@ __global__ void k_stage_sizes(const uint64_t *optr, uint32_t n, uint32_t wd, uin
 
 }  // namespace
 
+// Plain pair sampling (Section 6): the pair (x, y) of Gamma+(u), x before y in the
+// order, is kept iff (H2 >> 32) < t, H2 = mix64(mix64(seed ^ mix64(u << 32 | x)) ^
+// mix64(y)) on original ids; a masked copy of the staged cache is then counted.
+__device__ __forceinline__ bool pair_kept(uint64_t seed, uint32_t uid, uint32_t xid, uint32_t yid, uint64_t t) {
+    const uint64_t h = kc_mix64(kc_mix64(seed ^ kc_mix64(((uint64_t)uid << 32) | xid)) ^ kc_mix64((uint64_t)yid));
+    return (h >> 32) < t;
+}
+
+// one-wave tier rows (root-local bits), one thread per row; rows of larger roots are unused
+__global__ void k_pair_mask_rows(const uint64_t *optr, const uint32_t *ocol, const uint32_t *rank2id, uint32_t n,
+                                 uint64_t m, uint32_t wd, const uint64_t *in, uint64_t *out, uint64_t seed, uint64_t t) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    uint32_t lo = 0, hi = n;  // the root owning slot e: the last rank with optr[u] <= e
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (optr[mid] <= e) lo = mid; else hi = mid;
+    }
+    const uint64_t b = optr[lo], d = optr[lo + 1] - b, i = e - b;
+    // only rows of staged roots (2 <= d <= wd) hold data; a root of out-degree 1 is
+    // never staged and its slot is uninitialised.  Bits are kept to the row's later
+    // members i < j < d, so no read leaves the root's out-list.
+    uint64_t x = 0, kept = 0;
+    if (d >= 2 && d <= wd) x = in[e] & (d >= 64 ? ~0ull : ((1ull << d) - 1ull)) & ~((2ull << i) - 1ull);  // i < d <= 64
+    if (x) {
+        const uint32_t uid = rank2id[lo], xid = rank2id[ocol[e]];
+        while (x) {
+            const uint32_t j = (uint32_t)__builtin_ctzll(x);
+            x &= x - 1;
+            if (pair_kept(seed, uid, xid, rank2id[ocol[b + j]], t)) kept |= 1ull << j;
+        }
+    }
+    out[e] = kept;
+}
+
+// packed bitmaps of the roots above the one-wave tier (the wide part of the degree
+// queue), one block per root, one thread per row
+__global__ void k_pair_mask_bitmaps(const uint32_t *wide, const uint64_t *optr, const uint32_t *ocol,
+                                    const uint32_t *rank2id, const uint64_t *woff, const uint64_t *in, uint64_t *out,
+                                    uint64_t seed, uint64_t t) {
+    const uint32_t u = wide[blockIdx.x];
+    const uint64_t b = optr[u];
+    const uint32_t d = (uint32_t)(optr[u + 1] - b), W = (d + 63) / 64;
+    const uint32_t uid = rank2id[u];
+    for (uint32_t i = threadIdx.x; i < d; i += blockDim.x) {
+        const uint32_t xid = rank2id[ocol[b + i]];
+        const uint64_t off = woff[u] + tri_rowoff(i, W) - ((i + 1) >> 6);  // word l of row i at off + l
+        for (uint32_t l = (i + 1) >> 6; l < W; ++l) {
+            // bits of later members only: i < 64 l + bit < d
+            const uint32_t hi = d - 64 * l;  // >= 1 since l < W
+            uint64_t x = in[off + l] & (hi >= 64 ? ~0ull : ((1ull << hi) - 1ull)), kept = 0;
+            if (64 * l <= i) x &= ~((2ull << (i - 64 * l)) - 1ull);
+            while (x) {
+                const uint32_t bit = (uint32_t)__builtin_ctzll(x);
+                x &= x - 1;
+                if (pair_kept(seed, uid, xid, rank2id[ocol[b + 64 * l + bit]], t)) kept |= 1ull << bit;
+            }
+            out[off + l] = kept;
+        }
+    }
+}
+
 kc_status kc_stage_queue(const kc_graph *g, const kc_queue &q, int wd, uint64_t *res, kc_tmp &lrows, kc_tmp &wbits,
                          kc_tmp &woff, bool &cached) {
     cached = false;
@@ -1809,6 +1871,7 @@ kc_status kc_stage(kc_graph *g, int wd) {
         return KC_OK;
     }
     g->woff = woff;
+    g->stage_words = total;
     KC_TRY(kc_dev_alloc((void **)&g->wedges, (size_t)(n ? n : 1) * 4, s));
     KC_TRY(kc_dev_alloc((void **)&g->lrows, (size_t)(g->m ? g->m : 1) * 8, s));
     KC_TRY(kc_dev_alloc((void **)&g->wbits, (size_t)(total ? total : 1) * 8, s));
@@ -1942,7 +2005,9 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
         ac.cached = gm->staged == 1;
         staged_now = before != 1 && gm->staged == 1;
     }
-    if (staged_now && a.k == 3 && !a.colored && !a.per_root && !getenv("KC_TEST_TOTAL_BIAS")) {
+    if (a.sampled && !ac.cached)
+        return kc_fail(KC_ENOMEM, "pair sampling counts a masked copy of the staged cache, which is not kept here");
+    if (staged_now && a.k == 3 && !a.colored && !a.sampled && !a.per_root && !getenv("KC_TEST_TOTAL_BIAS")) {
         // the staging pass just left q_3 in the result block
         for (int e = 1; e < 6; ++e) KC_HIP(hipEventRecord(g->ev[e], s));
         uint64_t *h_res = kc_pinned_scratch();
@@ -1967,8 +2032,33 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
     size_t slice_words = 0;
     uint32_t scratch_blocks = 0;
     KC_TRY(kc_count_scratch(g, q, a.k, gscr, slice_words, scratch_blocks));
+    // pair sampling: the count reads a masked copy of the cache through a view of the handle
+    kc_tmp mrows, mbits;
+    kc_graph view;
+    const kc_graph *gc = g;
+    if (a.sampled) {
+        KC_TRY(kc_tmp_alloc(mrows, (size_t)(g->m ? g->m : 1) * 8, s));
+        KC_TRY(kc_tmp_alloc(mbits, (size_t)(g->stage_words ? g->stage_words : 1) * 8, s));
+        if (g->m)
+            hipLaunchKernelGGL(k_pair_mask_rows, dim3((unsigned)((g->m + 255) / 256)), dim3(256), 0, s,
+                               (const uint64_t *)g->optr, (const uint32_t *)g->ocol, (const uint32_t *)g->rank2id, g->n,
+                               g->m, (uint32_t)g->stage_wd, (const uint64_t *)g->lrows, mrows.as<uint64_t>(), a.seed,
+                               a.pair_t);
+        if (g->dq_ready && g->dq_wd == g->stage_wd && g->dq_wide)
+            hipLaunchKernelGGL(k_pair_mask_bitmaps, dim3(g->dq_wide), dim3(256), 0, s, (const uint32_t *)g->dq,
+                               (const uint64_t *)g->optr, (const uint32_t *)g->ocol, (const uint32_t *)g->rank2id,
+                               (const uint64_t *)g->woff, (const uint64_t *)g->wbits, mbits.as<uint64_t>(), a.seed,
+                               a.pair_t);
+        else if (g->dq_wide || !g->dq_ready)
+            return kc_fail(KC_ESTATE, "pair sampling needs the degree queue of the staged cache");
+        KC_HIP(hipGetLastError());
+        view = *g;
+        view.lrows = mrows.as<uint64_t>();
+        view.wbits = mbits.as<uint64_t>();
+        gc = &view;
+    }
     hipEvent_t tev[4] = {g->ev[2], g->ev[3], g->ev[4], g->ev[5]};
-    KC_TRY(kc_count_launch(g, q, ac, g->d_res, nullptr, 0, nullptr, gscr.as<uint64_t>(), slice_words, scratch_blocks,
+    KC_TRY(kc_count_launch(gc, q, ac, g->d_res, nullptr, 0, nullptr, gscr.as<uint64_t>(), slice_words, scratch_blocks,
                            s, tev));
     uint64_t *h_res = kc_pinned_scratch();
     KC_HIP(hipMemcpyAsync(h_res, g->d_res, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));

@@ -102,6 +102,7 @@ struct kc_graph {
     // keep their packed upper-triangular bitmap at wbits + woff[u].
     int staged = 0;  // 1 built, -1 not kept (memory), 0 not yet
     int stage_wd = 0;
+    uint64_t stage_words = 0;  // words at wbits
     uint64_t *lrows = nullptr, *wbits = nullptr, *woff = nullptr;
 
     // Workgroup-tier items for counts from k = 5 on (degree policy, staged
@@ -145,6 +146,8 @@ struct kc_count_args {
     int policy = KC_SCHED_DEGREE;
     int cached = 0;  // count from the handle's staged G+(u) cache
     int store = 0;   // stage G+(u) into the cache, count nothing
+    int sampled = 0;      // plain pair sampling: count a masked copy of the cache
+    uint64_t pair_t = 0;  // keep threshold on the pair hash's high 32 bits (2^32 keeps all)
 };
 kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *total, int *overflow);
 struct kc_queue;

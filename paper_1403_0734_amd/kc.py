@@ -20,7 +20,7 @@ KC_KMAX = 10
 
 # every symbol include/kc.h declares
 EXPORTS = [
-    "kc_graph_create", "kc_orient", "kc_count", "kc_count_colored", "kc_count_per_root",
+    "kc_graph_create", "kc_orient", "kc_count", "kc_count_colored", "kc_count_pair_sampled", "kc_count_per_root",
     "kc_count_batch", "kc_set_schedule", "kc_train_schedule", "kc_graph_info", "kc_get_csr",
     "kc_get_oriented", "kc_last_timings", "kc_graph_destroy", "kc_status_str",
     "kc_set_tuning", "kc_get_tuning", "kc_autotune", "kc_last_tier_timings",
@@ -60,6 +60,7 @@ def load(path: str = LIB_PATH):
         "kc_orient": (i32, [P]),
         "kc_count": (i32, [P, i32, ctypes.POINTER(u64)]),
         "kc_count_colored": (i32, [P, i32, u32, u64, i32, ctypes.POINTER(kc_estimate)]),
+        "kc_count_pair_sampled": (i32, [P, i32, ctypes.c_double, u64, ctypes.POINTER(kc_estimate)]),
         "kc_count_per_root": (i32, [P, i32, P, P]),
         "kc_count_batch": (i32, [P, u32, i32, P]),
         "kc_set_schedule": (i32, [P, i32, ctypes.c_char_p]),
@@ -124,6 +125,12 @@ def kc_count(g: int, k: int) -> int:
 def kc_count_colored(g: int, k: int, c: int, seed: int, scheme: int = KC_COLOR_PER_ROOT) -> kc_estimate:
     e = kc_estimate()
     check(load().kc_count_colored(g, k, c, seed, scheme, ctypes.byref(e)), "kc_count_colored")
+    return e
+
+
+def kc_count_pair_sampled(g: int, k: int, p: float, seed: int) -> kc_estimate:
+    e = kc_estimate()
+    check(load().kc_count_pair_sampled(g, k, float(p), seed, ctypes.byref(e)), "kc_count_pair_sampled")
     return e
 
 

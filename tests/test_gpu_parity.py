@@ -204,6 +204,39 @@ def test_workgroup_items(monkeypatch, mode):
         _close(h)
 
 
+@pytest.mark.parametrize("p", [1.0, 0.5, 0.2])
+def test_pair_sampling_raw_counts_match_oracle(p):
+    """Plain pair sampling (Section 6): the raw count of the masked cache equals the
+    oracle's, bit for bit, on every tier (K130 has workgroup-tier roots); p = 1 is
+    the exact count; the estimate is raw over the exact keep probability."""
+    cases = [(SMALL[2], [3, 4]), (SMALL[1], None), (SMALL[10], None), (SMALL[12], None), (MULTI_TILE[0], None)]
+    for el, ks in cases:
+        og = O.OracleGraph.from_edgelist(el)
+        h = device_graph(el)
+        for k in ks or [k for k in bounded_ks(og, 3, 5, budget=2e6)]:
+            for seed in [3, 2**63 + 17]:
+                announce(f"pair sampling {el.name} k={k} p={p}")
+                e = K.kc_count_pair_sampled(h, k, p, seed)
+                raw = og.count_pair_sampled(k, p, seed)
+                assert e.raw == raw, (el.name, k, p, seed)
+                ex = (k - 1) * (k - 2) // 2
+                assert e.scale_exponent == ex
+                keep = O.pair_threshold(p) / 2**32
+                assert e.estimate == pytest.approx(raw / keep ** ex, rel=1e-12)
+                if p == 1.0:
+                    assert raw == og.count(k) and e.estimate_fits_u64 and e.estimate_u64 == raw
+        _close(h)
+
+
+def test_pair_sampling_needs_the_cache(monkeypatch):
+    monkeypatch.setenv("KC_STAGE_CACHE", "0")
+    h = device_graph(SMALL[10])
+    with pytest.raises(K.KcError) as err:
+        K.kc_count_pair_sampled(h, 4, 0.5, 1)
+    assert err.value.status == K.KC_ENOMEM
+    _close(h)
+
+
 def test_repeat_runs_identical():
     el = SMALL[12]
     h = device_graph(el)
