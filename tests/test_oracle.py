@@ -298,6 +298,24 @@ def test_pair_sampling_p_one_is_exact(el):
         assert g.count_pair_sampled(k, 1.0, 99) == g.count(k), k
 
 
+def test_pair_hash_is_the_documented_composition():
+    """The pair hash composes the SplitMix64 finaliser (pinned by its published
+    vectors) as documented: H2 = mix64(mix64(seed ^ mix64(u << 32 | x)) ^ mix64(y));
+    the keep rule (H2 >> 32) < floor(p 2^32) keeps a fraction p of the pairs."""
+    rng = np.random.default_rng(7)
+    M = 2**64 - 1
+    for _ in range(200):
+        seed = int(rng.integers(0, 2**63)) * 2 + int(rng.integers(0, 2))
+        u, x, y = (int(v) for v in rng.integers(0, 2**32, 3))
+        h1 = O.mix64(seed ^ O.mix64(((u << 32) | x) & M))
+        assert O.hash_root(seed, u, x) == h1
+        assert O.hash_pair(seed, u, x, y) == O.mix64(h1 ^ O.mix64(y))
+    for p in [0.1, 0.5, 0.9]:
+        t = O.pair_threshold(p)
+        kept = sum((O.hash_pair(3, 5, x, x + 1) >> 32) < t for x in range(20000)) / 20000
+        assert abs(kept - p) < 0.02, (p, kept)
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_pair_sampling_bruteforce(seed):
     """k-subset form (Section 6, plain pair sampling): a clique S with smallest node
