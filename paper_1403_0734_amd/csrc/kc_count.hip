@@ -1581,8 +1581,52 @@ DevInfo dev_info(int device) {
 
 template <int K, int MODE>
 void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors, const DevInfo &di, hipStream_t s,
-                  uint64_t *gscratch, size_t slice_words, uint32_t scratch_blocks, hipEvent_t *ev) {
+                  uint64_t *gscratch, size_t slice_words, uint32_t scratch_blocks, hipEvent_t *ev, hipStream_t side,
+                  hipEvent_t fork, hipEvent_t join) {
     const kc_tuning_t &tu = kc_tuning_now();
+    // The one-wave tier goes first, on the side stream from k = 7 on (when there is one
+    // and the other tiers have roots): the tiers share no root and no counter, so the
+    // wave tier's blocks fill what the long workgroup launches leave free.  Measured:
+    // planted 4M at k = 8 takes 355 ms instead of 509; at k <= 6 the two tiers slow
+    // each other down (Chung-Lu 1M: no gain over the step, k = 5 and staging slower).
+    // ev: [0] scratch start, [1] scratch end / workgroup start, [2] workgroup end,
+    // [3] all done (after the join), [4] [5] the one-wave tier.
+    const bool split =
+        K >= 7 && MODE != MODE_STORE && side && fork && join && q.count[0] && (q.count[1] || q.count[2]);
+    hipStream_t ws = split ? side : s;
+    auto launch_wave = [&]() {
+        if (ev) (void)hipEventRecord(ev[4], ws);
+        if (q.count[0]) {
+            CountParams p = base;
+            p.queue = q.ptr[0];
+            p.count = q.count[0];
+            p.next = cursors + 0;
+            uint32_t blocks = (q.count[0] + WAVES - 1) / WAVES;
+            uint32_t per_cu = (uint32_t)(tu.wave_blocks_per_cu > 0 ? tu.wave_blocks_per_cu : 8);
+            int occ = 0;  // resident blocks per CU (registers, LDS)
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)&k_count_wave<K, MODE>, WG, 0) ==
+                    hipSuccess &&
+                occ > 0 && (uint32_t)occ < per_cu)
+                per_cu = (uint32_t)occ;
+            const uint32_t cap = (uint32_t)di.cus * per_cu;
+            if (blocks > cap) blocks = cap;
+            // chunk size follows the work per root: staging (reads every out-list) takes
+            // half-size chunks, counts from the cache at k <= 5 (a few cheap passes per
+            // chunk) larger ones, so that fewer queue fetches stall the wave
+            const uint32_t cd = base.chunk_div;
+            if (MODE == MODE_STORE) p.chunk_div = cd * 2;
+            else if (MODE == MODE_CACHED && K <= 4) p.chunk_div = cd / 4 ? cd / 4 : 1;
+            else if (MODE == MODE_CACHED && K == 5) p.chunk_div = cd / 2 ? cd / 2 : 1;
+            hipLaunchKernelGGL((k_count_wave<K, MODE>), dim3(blocks), dim3(WG), 0, ws, p);
+        }
+        if (ev) (void)hipEventRecord(ev[5], ws);
+    };
+    if (split) {
+        (void)hipEventRecord(fork, s);
+        (void)hipStreamWaitEvent(side, fork, 0);
+        launch_wave();
+        (void)hipEventRecord(join, side);
+    }
     if (ev) (void)hipEventRecord(ev[0], s);
     // scratch tier first: the largest roots
     if (q.count[2]) {
@@ -1659,29 +1703,8 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
         }
     }
     if (ev) (void)hipEventRecord(ev[2], s);
-    if (q.count[0]) {
-        CountParams p = base;
-        p.queue = q.ptr[0];
-        p.count = q.count[0];
-        p.next = cursors + 0;
-        uint32_t blocks = (q.count[0] + WAVES - 1) / WAVES;
-        uint32_t per_cu = (uint32_t)(tu.wave_blocks_per_cu > 0 ? tu.wave_blocks_per_cu : 8);
-        int occ = 0;  // resident blocks per CU (registers, LDS)
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)&k_count_wave<K, MODE>, WG, 0) ==
-                hipSuccess &&
-            occ > 0 && (uint32_t)occ < per_cu)
-            per_cu = (uint32_t)occ;
-        const uint32_t cap = (uint32_t)di.cus * per_cu;
-        if (blocks > cap) blocks = cap;
-        // chunk size follows the work per root: staging (reads every out-list) takes
-        // half-size chunks, counts from the cache at k <= 5 (a few cheap passes per
-        // chunk) larger ones, so that fewer queue fetches stall the wave
-        const uint32_t cd = base.chunk_div;
-        if (MODE == MODE_STORE) p.chunk_div = cd * 2;
-        else if (MODE == MODE_CACHED && K <= 4) p.chunk_div = cd / 4 ? cd / 4 : 1;
-        else if (MODE == MODE_CACHED && K == 5) p.chunk_div = cd / 2 ? cd / 2 : 1;
-        hipLaunchKernelGGL((k_count_wave<K, MODE>), dim3(blocks), dim3(WG), 0, s, p);
-    }
+    if (split) (void)hipStreamWaitEvent(s, join, 0);
+    else launch_wave();  // after the other tiers, on the same stream
     if (ev) (void)hipEventRecord(ev[3], s);
 }
 
@@ -1883,7 +1906,7 @@ kc_status kc_stage(kc_graph *g, int wd) {
     a.k = 3;
     a.store = 1;
     KC_TRY(kc_count_launch(g, q, a, g->d_res, nullptr, 0, nullptr, gscr.as<uint64_t>(), slice_words, scratch_blocks,
-                           s, nullptr));
+                           s, nullptr, true));
     g->staged = 1;
     g->stage_wd = wd;
     return KC_OK;
@@ -1924,7 +1947,9 @@ kc_status kc_count_scratch(const kc_graph *g, const kc_queue &q, int k, kc_tmp &
 // for batches.
 kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_args &a, uint64_t *res,
                           unsigned long long *gtotals, uint32_t ngraphs, const uint32_t *graph_of, uint64_t *gscratch,
-                          size_t slice_words, uint32_t scratch_blocks, hipStream_t s, hipEvent_t *tier_ev) {
+                          size_t slice_words, uint32_t scratch_blocks, hipStream_t s, hipEvent_t *tier_ev,
+                          bool use_side) {
+    hipStream_t side = use_side ? g->side : nullptr;
     const DevInfo di = dev_info(g->device);
     hipLaunchKernelGGL(k_fill_u64, dim3((KC_RES_WORDS + 63) / 64), dim3(64), 0, s, res, (size_t)KC_RES_WORDS, 0ull);
     if (gtotals)
@@ -1956,7 +1981,8 @@ kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_a
     if (a.store) {
         // staging into the cache does not depend on k; its total is q_3 (the edges of
         // every G+(u)), kept in res as a count would leave it
-        launch_tiers<3, MODE_STORE>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev);
+        launch_tiers<3, MODE_STORE>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev, side, g->fork,
+                                    g->join);
         if (!gtotals) hipLaunchKernelGGL(k_total_slots, dim3(1), dim3(64), 0, s, res);
         KC_HIP(hipGetLastError());
         return KC_OK;
@@ -1965,9 +1991,11 @@ kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_a
 #define KC_CASE(KK)                                                                                          \
     case KK:                                                                                                 \
         if (a.cached)                                                                                        \
-            launch_tiers<KK, MODE_CACHED>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev); \
+            launch_tiers<KK, MODE_CACHED>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev, \
+                                          side, g->fork, g->join);                                           \
         else                                                                                                 \
-            launch_tiers<KK, MODE_STAGE>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev);  \
+            launch_tiers<KK, MODE_STAGE>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev,  \
+                                         side, g->fork, g->join);                                            \
         break;
         KC_CASE(3)
         KC_CASE(4)
@@ -2009,7 +2037,7 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
         return kc_fail(KC_ENOMEM, "pair sampling counts a masked copy of the staged cache, which is not kept here");
     if (staged_now && a.k == 3 && !a.colored && !a.sampled && !a.per_root && !getenv("KC_TEST_TOTAL_BIAS")) {
         // the staging pass just left q_3 in the result block
-        for (int e = 1; e < 6; ++e) KC_HIP(hipEventRecord(g->ev[e], s));
+        for (int e = 1; e < 8; ++e) KC_HIP(hipEventRecord(g->ev[e], s));
         uint64_t *h_res = kc_pinned_scratch();
         KC_HIP(hipMemcpyAsync(h_res, g->d_res, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
         KC_TRY(kc_sync(s));
@@ -2057,9 +2085,9 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
         view.wbits = mbits.as<uint64_t>();
         gc = &view;
     }
-    hipEvent_t tev[4] = {g->ev[2], g->ev[3], g->ev[4], g->ev[5]};
+    hipEvent_t tev[6] = {g->ev[2], g->ev[3], g->ev[4], g->ev[5], g->ev[6], g->ev[7]};
     KC_TRY(kc_count_launch(gc, q, ac, g->d_res, nullptr, 0, nullptr, gscr.as<uint64_t>(), slice_words, scratch_blocks,
-                           s, tev));
+                           s, tev, true));
     uint64_t *h_res = kc_pinned_scratch();
     KC_HIP(hipMemcpyAsync(h_res, g->d_res, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     KC_TRY(kc_sync(s));
@@ -2068,7 +2096,7 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
     (void)hipEventElapsedTime(&t_count, g->ev[1], g->ev[5]);
     (void)hipEventElapsedTime(&tt[2], g->ev[2], g->ev[3]);
     (void)hipEventElapsedTime(&tt[1], g->ev[3], g->ev[4]);
-    (void)hipEventElapsedTime(&tt[0], g->ev[4], g->ev[5]);
+    (void)hipEventElapsedTime(&tt[0], g->ev[6], g->ev[7]);
     kc_graph *gm = const_cast<kc_graph *>(g);
     for (int t = 0; t < 3; ++t) gm->t_tier[t] = tt[t];
     gm->t_schedule = t_sched;

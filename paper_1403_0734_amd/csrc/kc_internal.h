@@ -115,7 +115,11 @@ struct kc_graph {
     uint32_t *wedges = nullptr;  // edges of G+(u) by rank, written when staging (roots above stage_wd)
 
     uint64_t serial = 0;  // unique per handle (batch plans are keyed by it)
-    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // second stream of the handle: the one-wave tier runs on it beside the
+    // workgroup and scratch tiers (fork / join events, no timing)
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     float t_schedule = 0.f, t_count = 0.f, t_total = 0.f;
     float t_tier[3] = {0.f, 0.f, 0.f};  // wave, workgroup, scratch kernels of the last count
 };
@@ -159,7 +163,7 @@ kc_status kc_count_scratch(const kc_graph *g, const kc_queue &q, int k, kc_tmp &
 kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_args &a, uint64_t *res,
                           unsigned long long *gtotals, uint32_t ngraphs, const uint32_t *graph_of, uint64_t *gscratch,
                           size_t slice_words, uint32_t scratch_blocks, hipStream_t s,
-                          hipEvent_t *tier_ev = nullptr);
+                          hipEvent_t *tier_ev = nullptr, bool use_side = false);
 
 // Stage the G+(u) of the roots in queue q of graph g into caches allocated here
 // (rows for roots with out-degree <= wd, packed bitmaps above), enqueued on g's
