@@ -123,9 +123,6 @@ static kc_status create_impl(const uint32_t *src, const uint32_t *dst, uint64_t 
     g->idbits = bits_for(n);
     g->serial = g_serial.fetch_add(1);
     for (auto &e : g->ev) KC_HIP(hipEventCreate(&e));
-    KC_HIP(hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking));  // default priority
-    KC_HIP(hipEventCreateWithFlags(&g->fork, hipEventDisableTiming));
-    KC_HIP(hipEventCreateWithFlags(&g->join, hipEventDisableTiming));
     KC_TRY(kc_dev_alloc((void **)&g->d_res, KC_RES_WORDS * sizeof(uint64_t), g->stream));
     if (!kc_pinned_scratch()) return kc_fail(KC_ENOMEM, "pinned host buffer");
     const uint32_t *ds = src, *dd = dst;

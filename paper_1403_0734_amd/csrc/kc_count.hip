@@ -1906,7 +1906,7 @@ kc_status kc_stage(kc_graph *g, int wd) {
     a.k = 3;
     a.store = 1;
     KC_TRY(kc_count_launch(g, q, a, g->d_res, nullptr, 0, nullptr, gscr.as<uint64_t>(), slice_words, scratch_blocks,
-                           s, nullptr, true));
+                           s, nullptr));
     g->staged = 1;
     g->stage_wd = wd;
     return KC_OK;
@@ -2085,9 +2085,23 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
         view.wbits = mbits.as<uint64_t>();
         gc = &view;
     }
+    // the second stream (one-wave tier beside the others, k >= 7) is created on first use,
+    // so handles that never count at k >= 7 (batches of many graphs) hold none
+    const bool side = a.k >= 7;
+    if (side && !g->side) {
+        kc_graph *gm = const_cast<kc_graph *>(g);
+        KC_HIP(hipStreamCreateWithFlags(&gm->side, hipStreamNonBlocking));  // default priority
+        KC_HIP(hipEventCreateWithFlags(&gm->fork, hipEventDisableTiming));
+        KC_HIP(hipEventCreateWithFlags(&gm->join, hipEventDisableTiming));
+        if (gc == &view) {
+            view.side = g->side;
+            view.fork = g->fork;
+            view.join = g->join;
+        }
+    }
     hipEvent_t tev[6] = {g->ev[2], g->ev[3], g->ev[4], g->ev[5], g->ev[6], g->ev[7]};
     KC_TRY(kc_count_launch(gc, q, ac, g->d_res, nullptr, 0, nullptr, gscr.as<uint64_t>(), slice_words, scratch_blocks,
-                           s, tev, true));
+                           s, tev, side));
     uint64_t *h_res = kc_pinned_scratch();
     KC_HIP(hipMemcpyAsync(h_res, g->d_res, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     KC_TRY(kc_sync(s));
