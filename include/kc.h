@@ -94,7 +94,9 @@ kc_status kc_orient(kc_graph *g);
  * stages every G+(u) into a device cache kept by the handle (about 8 bytes per edge
  * plus the bitmaps of roots above the one-wave limit; not kept when it would take
  * more than half the free device memory, or with KC_STAGE_CACHE=0); later counts of
- * any k and either colouring read it.  The staging pass itself yields q_3.
+ * any k and either colouring read it.  The staging pass itself yields q_3.  From
+ * k = 7 the handle runs its one-wave tier on a second stream of its own (created on
+ * first use, joined back before the call returns, destroyed with the handle).
  * KC_ESTATE if not oriented; KC_EOVERFLOW if q_k >= 2^64. */
 kc_status kc_count(const kc_graph *g, int32_t k, uint64_t *q_out);
 
