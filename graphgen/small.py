@@ -99,3 +99,18 @@ def planted_small(n: int, p: float, cliques, seed: int) -> EdgeList:
     for c in cliques:
         pairs += [(a, b) for a, b in itertools.combinations(sorted(c), 2)]
     return _el(n, pairs, f"planted({n},{p},{len(cliques)})")
+
+
+def hub_bipartite(na: int, nb: int, p: float, seed: int) -> EdgeList:
+    """Every node of A = [0, na) joined to every node of B = [na, na + nb), plus
+    G(nb, p) inside B (numpy PCG64 stream).  With nb > na, B's nodes have the larger
+    degrees, so every node of A keeps (almost) all of B as its high neighbours:
+    high-neighbourhoods of about nb nodes on a sparse graph."""
+    rng = np.random.default_rng(seed)
+    a = np.repeat(np.arange(na, dtype=np.uint64), nb)
+    b = np.tile(np.arange(na, na + nb, dtype=np.uint64), na)
+    iu, ju = np.triu_indices(nb, 1)
+    keep = rng.random(iu.shape[0]) < p
+    src = np.concatenate([a, iu[keep].astype(np.uint64) + na]).astype(np.uint32)
+    dst = np.concatenate([b, ju[keep].astype(np.uint64) + na]).astype(np.uint32)
+    return EdgeList(na + nb, src, dst, f"hub({na},{nb},{p},seed={seed})")

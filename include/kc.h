@@ -160,9 +160,16 @@ typedef struct {
     int32_t wg_blocks_per_cu;   /* workgroup-tier blocks per CU, 0 = as many as LDS allows (0..8) */
     int32_t wave_blocks_per_cu; /* persistent wave-tier blocks of 4 waves per CU (1..16) */
     int32_t queue_chunk_div;    /* queue chunk = roots / (workers * queue_chunk_div) (1..64) */
+    int32_t wg_dmax;            /* roots above wave_dmax with out-degree <= wg_dmax keep their bitmap in
+                                   LDS (workgroup tier), larger ones in a global-memory slice (scratch
+                                   tier); 0 = as large as LDS allows, else 64..65535 (lowered to the
+                                   LDS limit when above it) */
+    int32_t local_bits;         /* width of the local graphs that candidate sets of workgroup-tier roots
+                                   are compacted into, in nodes: 64 (one word per row) or 128 (two
+                                   words; used from k = 5); 0 = 128 */
 } kc_tuning;
 
-/* Set the tunables (NULL restores the defaults 64, 0, 8, 8); KC_EINVAL outside the ranges. */
+/* Set the tunables (NULL restores the defaults 64, 0, 8, 8, 0, 128); KC_EINVAL outside the ranges. */
 kc_status kc_set_tuning(const kc_tuning *t);
 kc_status kc_get_tuning(kc_tuning *t);
 

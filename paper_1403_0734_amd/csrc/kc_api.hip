@@ -215,15 +215,12 @@ kc_status kc_count_colored(const kc_graph *g, int32_t k, uint32_t c, uint64_t se
     KC_TRY(kc_count_impl(g, a, &raw, &ovf));
     if (ovf) return kc_fail(KC_EOVERFLOW, "raw colour-sampled count >= 2^64");
     const int e = scheme == KC_COLOR_PER_ROOT ? k - 2 : k - 1;
-    unsigned __int128 scale = 1, est = raw;
-    int fits128 = 1;
-    for (int i = 0; i < e; ++i) {
-        scale *= c;
-    }
-    // raw * c^e in 128 bits (raw < 2^64, c^e < 2^(32*8)): track overflow of 128 bits too
+    // raw * c^e exactly in 128 bits when it fits there (raw < 2^64, c^e < 2^(32 e)),
+    // else in long double
     long double estd = (long double)raw;
     for (int i = 0; i < e; ++i) estd *= (long double)c;
-    est = (unsigned __int128)raw;
+    unsigned __int128 est = (unsigned __int128)raw;
+    int fits128 = 1;
     for (int i = 0; i < e; ++i) {
         if (est != 0 && (unsigned __int128)c > (~(unsigned __int128)0) / est) {
             fits128 = 0;
@@ -231,7 +228,6 @@ kc_status kc_count_colored(const kc_graph *g, int32_t k, uint32_t c, uint64_t se
         }
         est *= c;
     }
-    (void)scale;
     out->raw = raw;
     out->scale_exponent = e;
     out->estimate = fits128 ? (double)est : (double)estd;
@@ -311,10 +307,16 @@ kc_status kc_set_tuning(const kc_tuning *t) {
         if (t->wave_blocks_per_cu < 1 || t->wave_blocks_per_cu > 16)
             return kc_fail(KC_EINVAL, "wave_blocks_per_cu in [1, 16]");
         if (t->queue_chunk_div < 1 || t->queue_chunk_div > 64) return kc_fail(KC_EINVAL, "queue_chunk_div in [1, 64]");
+        if (t->wg_dmax != 0 && (t->wg_dmax < 64 || t->wg_dmax > 65535))
+            return kc_fail(KC_EINVAL, "wg_dmax must be 0 or in [64, 65535]");
+        if (t->local_bits != 0 && t->local_bits != 64 && t->local_bits != 128)
+            return kc_fail(KC_EINVAL, "local_bits must be 0, 64 or 128");
         v.wave_dmax = t->wave_dmax;
         v.wg_blocks_per_cu = t->wg_blocks_per_cu;
         v.wave_blocks_per_cu = t->wave_blocks_per_cu;
         v.chunk_div = t->queue_chunk_div;
+        v.wg_dmax = t->wg_dmax;
+        v.local_bits = t->local_bits ? t->local_bits : 128;
     }
     g_tuning = v;
     return KC_OK;
@@ -326,6 +328,8 @@ kc_status kc_get_tuning(kc_tuning *t) {
     t->wg_blocks_per_cu = g_tuning.wg_blocks_per_cu;
     t->wave_blocks_per_cu = g_tuning.wave_blocks_per_cu;
     t->queue_chunk_div = g_tuning.chunk_div;
+    t->wg_dmax = g_tuning.wg_dmax;
+    t->local_bits = g_tuning.local_bits;
     return KC_OK;
 }
 

@@ -106,6 +106,8 @@ std::vector<uint64_t> plan_key(kc_graph *const *gs, uint32_t num, int k) {
     key.push_back((uint64_t)tu.wg_blocks_per_cu);
     key.push_back((uint64_t)tu.wave_blocks_per_cu);
     key.push_back((uint64_t)tu.chunk_div);
+    key.push_back((uint64_t)tu.wg_dmax);
+    key.push_back((uint64_t)tu.local_bits);
     return key;
 }
 
@@ -304,7 +306,7 @@ extern "C" kc_status kc_count_batch(kc_graph *const *gs, uint32_t num, int32_t k
 void kc_batch_forget(uint64_t serial) {
     std::lock_guard<std::mutex> lk(g_plan_mu);
     if (!g_plan) return;
-    for (size_t i = 0; i + 5 < g_plan->key.size(); ++i)
+    for (size_t i = 0; i < g_plan->num; ++i)  // the key starts with the handles' serials
         if (g_plan->key[i] == serial) {
             (void)kc_sync(g_plan->bg.stream);
             delete g_plan;
@@ -324,7 +326,7 @@ extern "C" kc_status kc_autotune(kc_graph *const *gs, uint32_t num, int32_t k, c
     snprintf(keybuf, sizeof(keybuf), "%s|graphs=%u|n=%llu|m=%llu|k=%d", arch_name(gs[0]->device).c_str(), num,
              (unsigned long long)N, (unsigned long long)M, k);
     const std::string key = keybuf;
-    // cache: one entry per line, "key\twave_dmax wg_blocks wave_blocks chunk_div seconds"
+    // cache: one entry per line, "key\twave_dmax wg_blocks wave_blocks chunk_div wg_dmax local_bits seconds"
     std::vector<std::string> lines;
     if (cache_path) {
         FILE *f = fopen(cache_path, "r");
@@ -339,8 +341,8 @@ extern "C" kc_status kc_autotune(kc_graph *const *gs, uint32_t num, int32_t k, c
                 if (tab != std::string::npos && l.substr(0, tab) == key) {
                     kc_tuning t;
                     double sec = 0;
-                    if (sscanf(l.c_str() + tab + 1, "%d %d %d %d %lf", &t.wave_dmax, &t.wg_blocks_per_cu,
-                               &t.wave_blocks_per_cu, &t.queue_chunk_div, &sec) == 5) {
+                    if (sscanf(l.c_str() + tab + 1, "%d %d %d %d %d %d %lf", &t.wave_dmax, &t.wg_blocks_per_cu,
+                               &t.wave_blocks_per_cu, &t.queue_chunk_div, &t.wg_dmax, &t.local_bits, &sec) == 7) {
                         fclose(f);
                         KC_TRY(kc_set_tuning(&t));
                         if (best) *best = t;
@@ -352,29 +354,33 @@ extern "C" kc_status kc_autotune(kc_graph *const *gs, uint32_t num, int32_t k, c
         }
     }
     std::vector<uint64_t> out(num);
+    // bin thresholds (the one-wave tier's out-degree limit), workgroup blocks per CU,
+    // wave blocks per CU, queue chunk divisor and the local-graph tile width
     const int wds[] = {24, 48, 64};
     const int wgb[] = {0, 2};
     const int wvb[] = {4, 8};
     const int cds[] = {4, 16};
-    kc_tuning bt{64, 0, 8, 8};
+    const int lbs[] = {64, 128};
+    kc_tuning bt{64, 0, 8, 8, 0, 128};
     double bsec = 1e30;
     for (int a : wds)
         for (int b : wgb)
             for (int c : wvb)
-                for (int d : cds) {
-                    kc_tuning t{a, b, c, d};
-                    KC_TRY(kc_set_tuning(&t));
-                    KC_TRY(kc_count_batch(gs, num, k, out.data()));  // builds, runs eagerly and captures
-                    const int reps = 3;
-                    const auto t0 = std::chrono::steady_clock::now();
-                    for (int r = 0; r < reps; ++r) KC_TRY(kc_count_batch(gs, num, k, out.data()));
-                    const double sec =
-                        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() / reps;
-                    if (sec < bsec) {
-                        bsec = sec;
-                        bt = t;
+                for (int d : cds)
+                    for (int e : lbs) {
+                        kc_tuning t{a, b, c, d, 0, e};
+                        KC_TRY(kc_set_tuning(&t));
+                        KC_TRY(kc_count_batch(gs, num, k, out.data()));  // builds, runs eagerly and captures
+                        const int reps = 3;
+                        const auto t0 = std::chrono::steady_clock::now();
+                        for (int r = 0; r < reps; ++r) KC_TRY(kc_count_batch(gs, num, k, out.data()));
+                        const double sec =
+                            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() / reps;
+                        if (sec < bsec) {
+                            bsec = sec;
+                            bt = t;
+                        }
                     }
-                }
     KC_TRY(kc_set_tuning(&bt));
     if (best) *best = bt;
     if (cache_path) {
@@ -382,8 +388,8 @@ extern "C" kc_status kc_autotune(kc_graph *const *gs, uint32_t num, int32_t k, c
         if (!f) return kc_fail(KC_EINVAL, "cannot write %s", cache_path);
         for (const std::string &l : lines)
             if (l.substr(0, l.find('\t')) != key) fprintf(f, "%s\n", l.c_str());
-        fprintf(f, "%s\t%d %d %d %d %.9f\n", key.c_str(), bt.wave_dmax, bt.wg_blocks_per_cu, bt.wave_blocks_per_cu,
-                bt.queue_chunk_div, bsec);
+        fprintf(f, "%s\t%d %d %d %d %d %d %.9f\n", key.c_str(), bt.wave_dmax, bt.wg_blocks_per_cu,
+                bt.wave_blocks_per_cu, bt.queue_chunk_div, bt.wg_dmax, bt.local_bits, bsec);
         fclose(f);
     }
     return KC_OK;

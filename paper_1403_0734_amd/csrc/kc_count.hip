@@ -146,6 +146,7 @@ struct CountParams {
     size_t slice_words;   // u64 words per slice
     uint32_t dcap;        // largest d the workgroup layout holds
     uint32_t chunk_div;   // queue chunk = count / (workers * chunk_div)
+    uint32_t local2;      // workgroup tier, k >= 5: compact candidate sets of 65..128 nodes into two-word local graphs
     // workgroup tier, split roots: item = rank << 32 | part << 16 | parts (null: queue, one part each)
     const uint64_t *items;
     // batches: graph of every rank and one total per graph (null for one graph)
@@ -1343,7 +1344,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                     local_count<LC_REG_WG, false>(A, sN, K - 2, acc);
                     return;
                 }
-                if (K >= 5 && pc <= 128) {
+                if (K >= 5 && p.local2 && pc <= 128) {
                     const uint32_t sN = compact_local2(ri, lo0, W, bm, W, A2);
                     local_count2(A2, sN, K - 2, acc);
                     return;
@@ -1398,7 +1399,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                     } else if (cpc <= 64) {
                         const uint32_t sN = compact_local(nxt, clo, W, bm, W, A);
                         local_count<LC_REG_WG, false>(A, sN, cn, acc);
-                    } else if (K >= 5 && cpc <= 128) {
+                    } else if (K >= 5 && p.local2 && cpc <= 128) {
                         const uint32_t sN = compact_local2(nxt, clo, W, bm, W, A2);
                         local_count2(A2, sN, cn, acc);
                     } else {
@@ -1912,7 +1913,8 @@ kc_status kc_stage(kc_graph *g, int wd) {
     return KC_OK;
 }
 
-// Largest out-degree whose workgroup layout (packed bitmap included) fits in LDS.
+// Largest out-degree of the workgroup tier: the largest whose workgroup layout
+// (packed bitmap included) fits in LDS, or the wg_dmax tunable when that is lower.
 uint32_t kc_lds_dcap(int device, int k) {
     const DevInfo di = dev_info(device);
     const size_t budget = di.lds_max - wg_static_lds(k) - 512;
@@ -1921,6 +1923,8 @@ uint32_t kc_lds_dcap(int device, int k) {
         const uint32_t mid = (lo + hi + 1) / 2;
         if (wg_layout(mid, k).bytes <= budget) lo = mid; else hi = mid - 1;
     }
+    const int cap = kc_tuning_now().wg_dmax;
+    if (cap > 0 && (uint32_t)cap < lo) lo = (uint32_t)cap;
     return lo;
 }
 
@@ -1955,7 +1959,9 @@ kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_a
     if (gtotals)
         hipLaunchKernelGGL(k_fill_u64, dim3((ngraphs + 255) / 256), dim3(256), 0, s, (uint64_t *)gtotals,
                            (size_t)ngraphs, 0ull);
-    const char *bias = getenv("KC_TEST_TOTAL_BIAS");  // test hook: forces the overflow path
+    // test hook, read once per process: the total starts at this value, which forces the
+    // carry check of the reduction
+    static const char *const bias = getenv("KC_TEST_TOTAL_BIAS");
     if (bias && !gtotals)
         hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, res, (size_t)1, (uint64_t)strtoull(bias, nullptr, 0));
     CountParams p{};
@@ -1971,6 +1977,7 @@ kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_a
     p.c = a.c;
     p.seed = a.seed;
     p.chunk_div = (uint32_t)(kc_tuning_now().chunk_div > 0 ? kc_tuning_now().chunk_div : 8);
+    p.local2 = kc_tuning_now().local_bits >= 128 ? 1u : 0u;
     p.graph_of = graph_of;
     p.gtotals = gtotals;
     p.lrows = g->lrows;
@@ -2035,7 +2042,8 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
     }
     if (a.sampled && !ac.cached)
         return kc_fail(KC_ENOMEM, "pair sampling counts a masked copy of the staged cache, which is not kept here");
-    if (staged_now && a.k == 3 && !a.colored && !a.sampled && !a.per_root && !getenv("KC_TEST_TOTAL_BIAS")) {
+    static const bool biased = getenv("KC_TEST_TOTAL_BIAS") != nullptr;  // the test hook above
+    if (staged_now && a.k == 3 && !a.colored && !a.sampled && !a.per_root && !biased) {
         // the staging pass just left q_3 in the result block
         for (int e = 1; e < 8; ++e) KC_HIP(hipEventRecord(g->ev[e], s));
         uint64_t *h_res = kc_pinned_scratch();

@@ -158,8 +158,9 @@ struct kc_queue;
 uint32_t kc_lds_dcap(int device, int k);
 kc_status kc_count_scratch(const kc_graph *g, const kc_queue &q, int k, kc_tmp &gscr, size_t &slice_words,
                            uint32_t &blocks);
-// tier_ev (may be null): 4 events recorded before the scratch, workgroup and wave
-// tier launches and after the last one.
+// tier_ev (may be null): 6 events: [0] before the scratch tier, [1] after it (before
+// the workgroup tier), [2] after the workgroup tier, [3] after every tier (the join),
+// [4] [5] around the one-wave tier.
 kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_args &a, uint64_t *res,
                           unsigned long long *gtotals, uint32_t ngraphs, const uint32_t *graph_of, uint64_t *gscratch,
                           size_t slice_words, uint32_t scratch_blocks, hipStream_t s,
@@ -182,6 +183,8 @@ struct kc_tuning_t {
     int wg_blocks_per_cu = 0;    // 0: as many as LDS allows (at most 8)
     int wave_blocks_per_cu = 8;  // persistent wave-tier blocks per CU
     int chunk_div = 8;           // queue chunk = roots / (workers * chunk_div), 1..64
+    int wg_dmax = 0;             // workgroup-tier out-degree limit (0: as LDS allows); larger roots go to scratch
+    int local_bits = 128;        // widest local graph candidate sets are compacted into (64 or 128 nodes)
 };
 const kc_tuning_t &kc_tuning_now();
 

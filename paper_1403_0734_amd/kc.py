@@ -40,7 +40,8 @@ class kc_estimate(ctypes.Structure):
 
 class kc_tuning(ctypes.Structure):
     _fields_ = [("wave_dmax", ctypes.c_int32), ("wg_blocks_per_cu", ctypes.c_int32),
-                ("wave_blocks_per_cu", ctypes.c_int32), ("queue_chunk_div", ctypes.c_int32)]
+                ("wave_blocks_per_cu", ctypes.c_int32), ("queue_chunk_div", ctypes.c_int32),
+                ("wg_dmax", ctypes.c_int32), ("local_bits", ctypes.c_int32)]
 
 
 _lib = None
@@ -157,11 +158,12 @@ def kc_train_schedule(gs, k: int, epochs: int, seed: int, weights_path: str) -> 
     return loss.value
 
 
-def kc_set_tuning(wave_dmax=64, wg_blocks_per_cu=0, wave_blocks_per_cu=8, queue_chunk_div=8, defaults=False):
+def kc_set_tuning(wave_dmax=64, wg_blocks_per_cu=0, wave_blocks_per_cu=8, queue_chunk_div=8, wg_dmax=0,
+                  local_bits=128, defaults=False):
     if defaults:
         check(load().kc_set_tuning(None), "kc_set_tuning")
         return
-    t = kc_tuning(wave_dmax, wg_blocks_per_cu, wave_blocks_per_cu, queue_chunk_div)
+    t = kc_tuning(wave_dmax, wg_blocks_per_cu, wave_blocks_per_cu, queue_chunk_div, wg_dmax, local_bits)
     check(load().kc_set_tuning(ctypes.byref(t)), "kc_set_tuning")
 
 

@@ -115,6 +115,113 @@ def test_tier_boundaries_complete_graphs():
         _close(h)
 
 
+def test_wide_search_closed_forms():
+    """First-level candidate sets above 128 nodes (the wide depth-first search of the
+    workgroup tier, from k = 5): K_400 and K_300 against C(n, k), and a complete
+    multipartite graph against the elementary symmetric polynomial of its parts."""
+    for n, ks in [(400, [5]), (300, [6])]:
+        h = device_graph(S.complete(n))
+        for k in ks:
+            announce(f"K{n} k={k} (wide search)")
+            assert K.kc_count(h, k) == math.comb(n, k), (n, k)
+        _close(h)
+    parts = [200, 150, 300, 90, 310]
+    h = device_graph(S.complete_multipartite(parts))
+    announce("multipartite k=5 (wide search)")
+    assert K.kc_count(h, 5) == math.prod(parts)
+    _close(h)
+
+
+def test_wide_search_dense_random():
+    """A dense G(500, 0.6): out-degrees up to about 275, first-level candidate sets of
+    about 165 nodes; totals and per-root counts at k = 5 against the oracle."""
+    el = S.random_graph(500, 0.6, 8)
+    og = O.OracleGraph.from_edgelist(el)
+    h = device_graph(el)
+    announce("G(500, 0.6) k=5")
+    assert K.kc_count(h, 5) == og.count(5)
+    c, _ = per_root(h, el.n, 5)
+    assert np.array_equal(c, og.count_per_root(5))
+    _close(h)
+
+
+@pytest.fixture
+def wg_cap():
+    """Lowers the workgroup tier's out-degree cap (the wg_dmax tunable) for one test,
+    so that roots above it take the scratch tier (bitmaps in global memory)."""
+    def set_cap(cap):
+        K.kc_set_tuning(wg_dmax=cap)
+    yield set_cap
+    K.kc_set_tuning(defaults=True)
+
+
+SCRATCH_GRAPHS = [SMALL[2], SMALL[10], SMALL[11], SMALL[12], MULTI_TILE[0]]
+
+
+@pytest.mark.parametrize("cache", ["1", "0"])
+@pytest.mark.parametrize("cap", [64, 72])
+def test_scratch_tier_under_lowered_cap(monkeypatch, wg_cap, cap, cache):
+    """The scratch tier (G+(u) bitmap in a global-memory slice per block) on ordinary
+    graphs: with the cap at 64 every root above the one-wave tier takes it, at 72 the
+    workgroup and scratch tiers share the roots.  Staged into the cache and counted
+    from it, or staged per call; exact totals k = 3..8, per-root counts, both
+    colourings and (cached) pair sampling against the oracle."""
+    monkeypatch.setenv("KC_STAGE_CACHE", cache)
+    wg_cap(cap)
+    for el in SCRATCH_GRAPHS:
+        og = O.OracleGraph.from_edgelist(el)
+        h = device_graph(el)
+        ks = bounded_ks(og, 3, 8, budget=5e6)
+        for k in ks:
+            announce(f"scratch cap={cap} cache={cache} {el.name} k={k}")
+            assert K.kc_count(h, k) == og.count(k), (el.name, k)
+        for scheme in (K.KC_COLOR_PER_ROOT, K.KC_COLOR_GLOBAL):
+            for k in ks[:4]:
+                e = K.kc_count_colored(h, k, 3, 77, scheme)
+                assert e.raw == og.count_colored(k, 3, 77, scheme), (el.name, k, scheme)
+        for k in sorted({ks[-1], min(5, ks[-1])}):
+            c, _ = per_root(h, el.n, k)
+            assert np.array_equal(c, og.count_per_root(k)), (el.name, k)
+        if cache == "1":
+            for k in ks[:3]:
+                e = K.kc_count_pair_sampled(h, k, 0.5, 9)
+                assert e.raw == og.count_pair_sampled(k, 0.5, 9), (el.name, k)
+        _close(h)
+
+
+@pytest.mark.parametrize("cache", ["1", "0"])
+def test_scratch_tier_natural(monkeypatch, cache):
+    """Out-degrees above what LDS holds (about 1280 to 1344 nodes, by k) with the
+    default tunables.  K_1400 against C(n, k); a hub graph (every node of A joined to
+    every node of B, |A| = 1400, |B| = 1401, G(1401, 0.05) inside B) whose 1400 roots
+    each keep 1401 high neighbours, against the oracle: exact k = 3..6, per-root
+    counts, both colourings and pair sampling."""
+    monkeypatch.setenv("KC_STAGE_CACHE", cache)
+    h = device_graph(S.complete(1400))
+    assert K.kc_graph_info(h)[2] == 1399
+    for k in (3, 4):
+        announce(f"K1400 k={k} cache={cache}")
+        assert K.kc_count(h, k) == math.comb(1400, k)
+    _close(h)
+    el = S.hub_bipartite(1400, 1401, 0.05, 3)
+    og = O.OracleGraph.from_edgelist(el)
+    h = device_graph(el)
+    assert K.kc_graph_info(h)[2] == og.max_outdeg() == 1401
+    for k in range(3, 7):
+        announce(f"hub k={k} cache={cache}")
+        assert K.kc_count(h, k) == og.count(k), k
+    for k in (4, 6):
+        c, _ = per_root(h, el.n, k)
+        assert np.array_equal(c, og.count_per_root(k)), k
+    for scheme in (K.KC_COLOR_PER_ROOT, K.KC_COLOR_GLOBAL):
+        e = K.kc_count_colored(h, 5, 2, 41, scheme)
+        assert e.raw == og.count_colored(5, 2, 41, scheme), scheme
+    if cache == "1":
+        e = K.kc_count_pair_sampled(h, 4, 0.5, 13)
+        assert e.raw == og.count_pair_sampled(4, 0.5, 13)
+    _close(h)
+
+
 def test_complete_multipartite_large():
     parts = [200, 150, 300, 90, 310]  # wide roots on every tier; e_4 ~ 1e10 cliques
     h = device_graph(S.complete_multipartite(parts))
@@ -228,6 +335,22 @@ def test_pair_sampling_raw_counts_match_oracle(p):
         _close(h)
 
 
+@pytest.mark.parametrize("p", [1.0, 0.5])
+def test_pair_sampling_first_call_at_k7(p):
+    """Pair sampling as the first k >= 7 call on a fresh handle: the handle's second
+    stream (the one-wave tier beside the workgroup tier from k = 7) is created inside
+    this call, on a graph with both tiers."""
+    el = SMALL[10]
+    og = O.OracleGraph.from_edgelist(el)
+    h = device_graph(el)
+    announce(f"pair sampling, first call at k=7, p={p}")
+    e = K.kc_count_pair_sampled(h, 7, p, 5)
+    assert e.raw == og.count_pair_sampled(7, p, 5)
+    if p == 1.0:
+        assert e.raw == og.count(7)
+    _close(h)
+
+
 def test_pair_sampling_needs_the_cache(monkeypatch):
     monkeypatch.setenv("KC_STAGE_CACHE", "0")
     h = device_graph(SMALL[10])
@@ -284,18 +407,41 @@ def test_error_paths():
     assert e.value.status == K.KC_EINVAL
 
 
-def test_overflow_is_reported(monkeypatch):
-    """The carry check of the global sum, forced from the host: the total starts
-    at 2^64 - 5, so adding the 10 triangles of K_5 must report KC_EOVERFLOW."""
+OVERFLOW_CHILD = """
+import sys
+sys.path.insert(0, sys.argv[1])
+from graphgen import small as S
+from paper_1403_0734_amd import kc as K
+def graph(el):
+    h = K.kc_graph_create(el.src, el.dst, el.m_in, el.n, False, None)
+    K.kc_orient(h)
+    return h
+print("K5", K.kc_count(graph(S.complete(5)), 3), flush=True)
+try:
+    print("K6", K.kc_count(graph(S.complete(6)), 3), flush=True)
+except K.KcError as e:
+    print("K6 status", e.status, flush=True)
+"""
+
+
+def test_overflow_is_reported():
+    """The carry check of the global sum, forced from the host: the library reads
+    KC_TEST_TOTAL_BIAS once per process and starts every total there.  At 2^64 - 11,
+    K_5's 10 triangles give 2^64 - 1 exactly and K_6's 20 must report KC_EOVERFLOW.
+    Runs in a child process (host input path, default stream) with that variable."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, KC_TEST_TOTAL_BIAS=str(2**64 - 11))
+    r = subprocess.run([sys.executable, "-c", OVERFLOW_CHILD, root], capture_output=True, text=True, env=env,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = r.stdout.split("\n")
+    assert f"K5 {2**64 - 1}" in lines, r.stdout
+    assert f"K6 status {K.KC_EOVERFLOW}" in lines, r.stdout
     h = device_graph(S.complete(5))
-    monkeypatch.setenv("KC_TEST_TOTAL_BIAS", str(2**64 - 5))
-    with pytest.raises(K.KcError) as e:
-        K.kc_count(h, 3)
-    assert e.value.status == K.KC_EOVERFLOW
-    monkeypatch.setenv("KC_TEST_TOTAL_BIAS", str(2**64 - 11))
-    assert K.kc_count(h, 3) == 2**64 - 1
-    monkeypatch.delenv("KC_TEST_TOTAL_BIAS")
-    assert K.kc_count(h, 3) == 10
+    assert K.kc_count(h, 3) == 10  # this process has no bias
     _close(h)
 
 

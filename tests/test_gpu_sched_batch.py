@@ -140,15 +140,18 @@ def test_batch_default_stream_and_destroy():
         K.kc_graph_destroy(h)
 
 
-@pytest.mark.parametrize("tuning", [(16, 0, 8, 8), (24, 2, 4, 4), (48, 1, 16, 64), (64, 8, 1, 1), (1, 0, 8, 8)])
+TUNING_FIELDS = ["wave_dmax", "wg_blocks_per_cu", "wave_blocks_per_cu", "queue_chunk_div", "wg_dmax", "local_bits"]
+
+
+@pytest.mark.parametrize("tuning", [(16, 0, 8, 8, 0, 128), (24, 2, 4, 4, 0, 64), (48, 1, 16, 64, 64, 128),
+                                    (64, 8, 1, 1, 0, 128), (1, 0, 8, 8, 100, 64)])
 def test_tunables_never_change_counts(stream, tuning):
     els = batch_graphs()
     want5 = [O.OracleGraph.from_edgelist(el).count(5) for el in els]
     hs = [graph_on(el, stream) for el in els]
     try:
         K.kc_set_tuning(*tuning)
-        assert K.kc_get_tuning() == dict(zip(["wave_dmax", "wg_blocks_per_cu", "wave_blocks_per_cu",
-                                               "queue_chunk_div"], tuning))
+        assert K.kc_get_tuning() == dict(zip(TUNING_FIELDS, tuning))
         assert K.kc_count_batch(hs, 5) == want5
         assert [K.kc_count(h, 5) for h in hs] == want5
     finally:
@@ -158,12 +161,13 @@ def test_tunables_never_change_counts(stream, tuning):
 
 
 def test_tuning_rejects_bad_values():
-    for bad in [(0, 0, 8, 8), (65, 0, 8, 8), (64, 9, 8, 8), (64, 0, 0, 8), (64, 0, 8, 65)]:
+    for bad in [(0, 0, 8, 8), (65, 0, 8, 8), (64, 9, 8, 8), (64, 0, 0, 8), (64, 0, 8, 65), (64, 0, 8, 8, 63),
+                (64, 0, 8, 8, 65536), (64, 0, 8, 8, 0, 96)]:
         with pytest.raises(K.KcError) as e:
             K.kc_set_tuning(*bad)
         assert e.value.status == K.KC_EINVAL
     K.kc_set_tuning(defaults=True)
-    assert K.kc_get_tuning()["wave_dmax"] == 64
+    assert K.kc_get_tuning() == dict(zip(TUNING_FIELDS, (64, 0, 8, 8, 0, 128)))
 
 
 def test_autotune_cache(stream, tmp_path):

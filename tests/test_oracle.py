@@ -316,6 +316,22 @@ def test_pair_hash_is_the_documented_composition():
         assert abs(kept - p) < 0.02, (p, kept)
 
 
+def test_node_hash_is_the_documented_composition():
+    """The global colouring's node hash composes the SplitMix64 finaliser (pinned by
+    its published vectors) as documented: H(seed, x) = mix64(seed ^ mix64(x)), with
+    the id zero-extended to 64 bits and the colour taken by multiply-high."""
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        seed = int(rng.integers(0, 2**63)) * 2 + int(rng.integers(0, 2))
+        x = int(rng.integers(0, 2**32))
+        h = O.hash_node(seed, x)
+        assert h == O.mix64(seed ^ O.mix64(x))
+        for c in (1, 2, 3, 8, 1000):
+            assert O.color(h, c) == ((h >> 32) * c) >> 32
+    # the node colour does not depend on anything but (seed, x): two seeds differ
+    assert sum(O.hash_node(1, x) == O.hash_node(2, x) for x in range(1000)) == 0
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_pair_sampling_bruteforce(seed):
     """k-subset form (Section 6, plain pair sampling): a clique S with smallest node
