@@ -140,6 +140,23 @@ kc_status kc_count_per_root(const kc_graph *g, int32_t k, uint64_t *dev_counts, 
  * num <= 65536. */
 kc_status kc_count_batch(kc_graph *const *gs, uint32_t num, int32_t k, uint64_t *q_out);
 
+/* Exact q_k (3 <= k <= KC_KMAX) with no device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  The same kernels and result as kc_count, on a handle that an
+ * earlier kc_count (any k >= 3) has prepared; KC_ESTATE otherwise.  It counts from
+ * the handle's staged cache when kept, and always with the degree queue (counts do
+ * not depend on the schedule).
+ *   - dev_out: caller device memory of two uint64: [0] q_k, [1] 1 if q_k >= 2^64
+ *     (then [0] is not the count), else 0.
+ *   - Enqueued on the handle's stream and not waited for: dev_out holds the result
+ *     once the stream has reached this call.  Nothing is read back to the host.
+ *   - Scratch: one 64 MiB device array per GPU, held from the first call on that
+ *     GPU until the process ends.  KC_EINVAL when a root's scratch-tier slice does
+ *     not fit in it (out-degrees above about 32000).
+ *   - Every call on a GPU shares that array: calls that overlap on one GPU (other
+ *     streams, other threads) race. */
+kc_status kc_count_noalloc(const kc_graph *g, int32_t k, uint64_t *dev_out);
+
 /* Scheduling policy for later counts.  For KC_SCHED_LEARNED, weights_path names a
  * weight file written by kc_train_schedule (NULL keeps the weights already loaded). */
 kc_status kc_set_schedule(kc_graph *g, int32_t policy, const char *weights_path);

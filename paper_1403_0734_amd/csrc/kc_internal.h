@@ -208,7 +208,12 @@ struct kc_queue {
     uint32_t wg_ncls = 0;
     uint32_t wg_cls_off[KC_WG_CLASSES], wg_cls_cnt[KC_WG_CLASSES], wg_cls_dmax[KC_WG_CLASSES];
 };
-kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_max, kc_queue &q);
+// no_alloc: degree policy only, from the handle's degree queue and work items as they
+// already are (KC_ESTATE when the degree queue is not built); nothing is allocated,
+// and heavy roots stay whole when the handle holds no work items for this tier.
+kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_max, kc_queue &q,
+                         bool no_alloc = false);
+size_t kc_scratch_slice_words(uint32_t dmax, int k);
 kc_status kc_features(const kc_graph *g, float *d_feat, hipStream_t s);
 
 // ----------------------------------------------------------------------------

@@ -341,7 +341,7 @@ kc_status build_degree_cache(kc_graph *g, uint32_t wd) {
 
 kc_status kc_predict_work(const kc_graph *g, int k, float *d_pred, hipStream_t s);
 
-kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_max, kc_queue &q) {
+kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_max, kc_queue &q, bool no_alloc) {
     hipStream_t s = g->stream;
     const uint32_t n = g->n;
     for (int t = 0; t < 3; ++t) {
@@ -353,9 +353,13 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
     wd = wd < 1 ? 1 : (wd > 64 ? 64 : wd);
     if ((uint32_t)wd > d_lds_max) wd = (int)d_lds_max;
 
+    if (no_alloc) policy = KC_SCHED_DEGREE;
     if (policy == KC_SCHED_DEGREE) {
         kc_graph *gm = const_cast<kc_graph *>(g);
-        if (!g->dq_ready || g->dq_wd != wd) KC_TRY(build_degree_cache(gm, (uint32_t)wd));
+        if (!g->dq_ready || g->dq_wd != wd) {
+            if (no_alloc) return kc_fail(KC_ESTATE, "the handle's degree queue is not built (count once with kc_count)");
+            KC_TRY(build_degree_cache(gm, (uint32_t)wd));
+        }
         const uint64_t *hist = g->dq_hist;
         const uint32_t dmax = g->max_outdeg;
         uint32_t scratch = 0, narrow = 0;
@@ -407,12 +411,14 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
         const char *wo = getenv("KC_WORK_ORDER");
         if (k >= 5 && q.count[1] && g->staged == 1 && g->stage_wd == wd && g->wedges && !(wo && wo[0] == '0')) {
             const uint32_t first = (uint32_t)(q.ptr[1] - g->dq);
-            if (!g->wq_ready || g->wq_first != first || g->wq_roots != q.count[1])
-                KC_TRY(build_work_items(gm, first, q.count[1]));
+            const bool have = g->wq_ready && g->wq_first == first && g->wq_roots == q.count[1];
+            if (!have && no_alloc) return KC_OK;  // whole roots
+            if (!have) KC_TRY(build_work_items(gm, first, q.count[1]));
             q.wg_items = g->wq;
             q.wg_item_count = g->wq_count;
             return KC_OK;
         }
+        if (no_alloc) return KC_OK;
         // KC_DEGREE_SPLIT: 0 turns the split off, n > 0 sets 2^n nodes per item from k = 6 on
         const char *se = getenv("KC_DEGREE_SPLIT");
         const int sn = se ? atoi(se) : 6;

@@ -23,7 +23,7 @@ EXPORTS = [
     "kc_graph_create", "kc_orient", "kc_count", "kc_count_colored", "kc_count_pair_sampled", "kc_count_per_root",
     "kc_count_batch", "kc_set_schedule", "kc_train_schedule", "kc_graph_info", "kc_get_csr",
     "kc_get_oriented", "kc_last_timings", "kc_graph_destroy", "kc_status_str",
-    "kc_set_tuning", "kc_get_tuning", "kc_autotune", "kc_last_tier_timings",
+    "kc_set_tuning", "kc_get_tuning", "kc_autotune", "kc_last_tier_timings", "kc_count_noalloc",
 ]
 
 
@@ -63,6 +63,7 @@ def load(path: str = LIB_PATH):
         "kc_count_colored": (i32, [P, i32, u32, u64, i32, ctypes.POINTER(kc_estimate)]),
         "kc_count_pair_sampled": (i32, [P, i32, ctypes.c_double, u64, ctypes.POINTER(kc_estimate)]),
         "kc_count_per_root": (i32, [P, i32, P, P]),
+        "kc_count_noalloc": (i32, [P, i32, P]),
         "kc_count_batch": (i32, [P, u32, i32, P]),
         "kc_set_schedule": (i32, [P, i32, ctypes.c_char_p]),
         "kc_train_schedule": (i32, [P, u32, i32, i32, u64, ctypes.c_char_p, ctypes.POINTER(ctypes.c_float)]),
@@ -137,6 +138,12 @@ def kc_count_pair_sampled(g: int, k: int, p: float, seed: int) -> kc_estimate:
 
 def kc_count_per_root(g: int, k: int, dev_counts, dev_work=None):
     check(load().kc_count_per_root(g, k, _ptr(dev_counts), _ptr(dev_work)), "kc_count_per_root")
+
+
+def kc_count_noalloc(g: int, k: int, dev_out):
+    """Enqueue an exact count that allocates nothing; dev_out: device uint64[2]
+    (q_k, overflow flag), valid once the handle's stream reaches this call."""
+    check(load().kc_count_noalloc(g, k, _ptr(dev_out)), f"kc_count_noalloc(k={k})")
 
 
 def kc_count_batch(gs, k: int) -> list:
