@@ -57,11 +57,22 @@ enum {
                               k nodes share a colour, probability c^-(k-1) */
 };
 
-/* Scheduling policies (kc_set_schedule). */
+/* Scheduling policies (kc_set_schedule); counts never depend on them. */
 enum {
-    KC_SCHED_DEGREE = 0,  /* tier by out-degree, queue ordered by out-degree descending */
-    KC_SCHED_LEARNED = 1  /* tier and order from an MLP's predicted per-root work */
+    KC_SCHED_DEGREE = 0,  /* plain degree binning: tier by out-degree, queue ordered by out-degree
+                             descending, every root one work item */
+    KC_SCHED_LEARNED = 1, /* from k = 5, the workgroup tier's roots ordered and split over several
+                             work items (Section 7) by an MLP's predicted per-root work, and
+                             one-wave roots with large predicted work promoted to the workgroup
+                             tier; the degree queue below k = 5 */
+    KC_SCHED_EDGES = 2    /* the default: as the degree policy, but from k = 5 the workgroup tier's
+                             roots ordered and split by an estimate from the edges of G+(u) (c^1.5/d^2
+                             for c edges and d nodes), known once the handle has staged G+(u) */
 };
+
+/* Parameters of the scheduler MLP (8 -> 32 -> 32 -> 1, ReLU, fp32), in this order:
+ * W1[32][8], b1[32], W2[32][32], b2[32], w3[32], b3. */
+#define KC_MLP_PARAMS 1377
 
 /* Largest clique size the counting kernels accept. */
 #define KC_KMAX 10
@@ -161,6 +172,29 @@ kc_status kc_count_noalloc(const kc_graph *g, int32_t k, uint64_t *dev_out);
  * weight file written by kc_train_schedule (NULL keeps the weights already loaded). */
 kc_status kc_set_schedule(kc_graph *g, int32_t policy, const char *weights_path);
 
+/* The scheduler MLP's predictions with the handle's loaded weights (KC_ESTATE
+ * without): dev_pred[n] (device, by original id) = the predicted log(1 + W(u, k)),
+ * W the per-root work kc_count_per_root reports, for every root with out-degree
+ * >= k-1 (0 for the others); dev_feat[n][8] (device, may be NULL) = the eight raw
+ * features it read: log1p d+(u), log1p sum of d+ over Gamma+(u), log1p max d+ over
+ * Gamma+(u), log1p d(u), log1p e+(u), e+(u) / C(d+(u), 2), k / 10, and
+ * log C(d+(u), k-1) + C(k-1, 2) log(e+(u) / C(d+(u), 2)) clamped to [-10, 60] (-10
+ * when undefined), with e+(u) the edges of G+(u).  3 <= k <= KC_KMAX. */
+kc_status kc_predict_work(const kc_graph *g, int32_t k, float *dev_pred, float *dev_feat);
+
+/* One training step of the scheduler MLP, the kernels kc_train_schedule runs per
+ * mini-batch: the gradient of 0.5 * mean over the count samples of (y - t)^2, with
+ * y the MLP's output for the standardised features dev_x[count][8] and dev_t[count]
+ * the standardised labels, then one Adam update (beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias correction at `step` >= 1) of dev_params[KC_MLP_PARAMS] with its moment
+ * vectors dev_adam_m, dev_adam_v (same size; zero before step 1).  dev_grad
+ * (KC_MLP_PARAMS, may be NULL) receives the gradient; *loss (host, may be NULL) the
+ * batch loss before the update.  All device pointers; runs on hip_stream (NULL = the
+ * default stream) and has completed when the call returns. */
+kc_status kc_mlp_step(float *dev_params, float *dev_adam_m, float *dev_adam_v, int32_t step, float lr,
+                      const float *dev_x, const float *dev_t, uint32_t count, float *dev_grad, float *loss,
+                      void *hip_stream);
+
 /* Train the scheduler's MLP (8 features -> 32 -> 32 -> 1, ReLU, fp32) on the GPU
  * to predict log(1 + per-root work) (the work kc_count_per_root reports) of every
  * root with at least k'-1 high neighbours, for every clique size k' = 4..k, over
@@ -184,9 +218,11 @@ typedef struct {
     int32_t local_bits;         /* width of the local graphs that candidate sets of workgroup-tier roots
                                    are compacted into, in nodes: 64 (one word per row) or 128 (two
                                    words; used from k = 5); 0 = 128 */
+    int32_t wg_waves;           /* waves per workgroup-tier block: 4, 8 or 16, or 0 = per launch, the
+                                   shape that keeps the most waves resident (LDS, registers) */
 } kc_tuning;
 
-/* Set the tunables (NULL restores the defaults 64, 0, 8, 8, 0, 128); KC_EINVAL outside the ranges. */
+/* Set the tunables (NULL restores the defaults 64, 0, 8, 8, 0, 128, 0); KC_EINVAL outside the ranges. */
 kc_status kc_set_tuning(const kc_tuning *t);
 kc_status kc_get_tuning(kc_tuning *t);
 

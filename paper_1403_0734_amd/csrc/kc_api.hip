@@ -104,6 +104,10 @@ void kc_graph_destroy(kc_graph *g) {
                     g->mlp,    g->d_res, g->dq,  g->tri,   g->lrows, g->wbits, g->woff, g->feat, g->wq, g->wedges};
     for (void *b : bufs)
         kc_cache_free(b, g->stream);
+    for (auto &L : g->lq) {
+        kc_cache_free(L.queue, g->stream);
+        kc_cache_free(L.items, g->stream);
+    }
     (void)kc_sync(g->stream);
     delete[] g->dq_hist;
     for (hipEvent_t e : g->ev)
@@ -311,12 +315,15 @@ kc_status kc_set_tuning(const kc_tuning *t) {
             return kc_fail(KC_EINVAL, "wg_dmax must be 0 or in [64, 65535]");
         if (t->local_bits != 0 && t->local_bits != 64 && t->local_bits != 128)
             return kc_fail(KC_EINVAL, "local_bits must be 0, 64 or 128");
+        if (t->wg_waves != 0 && t->wg_waves != 4 && t->wg_waves != 8 && t->wg_waves != 16)
+            return kc_fail(KC_EINVAL, "wg_waves must be 0, 4, 8 or 16");
         v.wave_dmax = t->wave_dmax;
         v.wg_blocks_per_cu = t->wg_blocks_per_cu;
         v.wave_blocks_per_cu = t->wave_blocks_per_cu;
         v.chunk_div = t->queue_chunk_div;
         v.wg_dmax = t->wg_dmax;
         v.local_bits = t->local_bits ? t->local_bits : 128;
+        v.wg_waves = t->wg_waves;
     }
     g_tuning = v;
     return KC_OK;
@@ -330,6 +337,7 @@ kc_status kc_get_tuning(kc_tuning *t) {
     t->queue_chunk_div = g_tuning.chunk_div;
     t->wg_dmax = g_tuning.wg_dmax;
     t->local_bits = g_tuning.local_bits;
+    t->wg_waves = g_tuning.wg_waves;
     return KC_OK;
 }
 

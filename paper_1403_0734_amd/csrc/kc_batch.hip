@@ -108,6 +108,7 @@ std::vector<uint64_t> plan_key(kc_graph *const *gs, uint32_t num, int k) {
     key.push_back((uint64_t)tu.chunk_div);
     key.push_back((uint64_t)tu.wg_dmax);
     key.push_back((uint64_t)tu.local_bits);
+    key.push_back((uint64_t)tu.wg_waves);
     return key;
 }
 
@@ -326,7 +327,7 @@ extern "C" kc_status kc_autotune(kc_graph *const *gs, uint32_t num, int32_t k, c
     snprintf(keybuf, sizeof(keybuf), "%s|graphs=%u|n=%llu|m=%llu|k=%d", arch_name(gs[0]->device).c_str(), num,
              (unsigned long long)N, (unsigned long long)M, k);
     const std::string key = keybuf;
-    // cache: one entry per line, "key\twave_dmax wg_blocks wave_blocks chunk_div wg_dmax local_bits seconds"
+    // cache: one entry per line, "key\twave_dmax wg_blocks wave_blocks chunk_div wg_dmax local_bits wg_waves seconds"
     std::vector<std::string> lines;
     if (cache_path) {
         FILE *f = fopen(cache_path, "r");
@@ -341,8 +342,9 @@ extern "C" kc_status kc_autotune(kc_graph *const *gs, uint32_t num, int32_t k, c
                 if (tab != std::string::npos && l.substr(0, tab) == key) {
                     kc_tuning t;
                     double sec = 0;
-                    if (sscanf(l.c_str() + tab + 1, "%d %d %d %d %d %d %lf", &t.wave_dmax, &t.wg_blocks_per_cu,
-                               &t.wave_blocks_per_cu, &t.queue_chunk_div, &t.wg_dmax, &t.local_bits, &sec) == 7) {
+                    if (sscanf(l.c_str() + tab + 1, "%d %d %d %d %d %d %d %lf", &t.wave_dmax, &t.wg_blocks_per_cu,
+                               &t.wave_blocks_per_cu, &t.queue_chunk_div, &t.wg_dmax, &t.local_bits, &t.wg_waves,
+                               &sec) == 8) {
                         fclose(f);
                         KC_TRY(kc_set_tuning(&t));
                         if (best) *best = t;
@@ -361,14 +363,14 @@ extern "C" kc_status kc_autotune(kc_graph *const *gs, uint32_t num, int32_t k, c
     const int wvb[] = {4, 8};
     const int cds[] = {4, 16};
     const int lbs[] = {64, 128};
-    kc_tuning bt{64, 0, 8, 8, 0, 128};
+    kc_tuning bt{64, 0, 8, 8, 0, 128, 0};
     double bsec = 1e30;
     for (int a : wds)
         for (int b : wgb)
             for (int c : wvb)
                 for (int d : cds)
                     for (int e : lbs) {
-                        kc_tuning t{a, b, c, d, 0, e};
+                        kc_tuning t{a, b, c, d, 0, e, 0};
                         KC_TRY(kc_set_tuning(&t));
                         KC_TRY(kc_count_batch(gs, num, k, out.data()));  // builds, runs eagerly and captures
                         const int reps = 3;
@@ -388,8 +390,8 @@ extern "C" kc_status kc_autotune(kc_graph *const *gs, uint32_t num, int32_t k, c
         if (!f) return kc_fail(KC_EINVAL, "cannot write %s", cache_path);
         for (const std::string &l : lines)
             if (l.substr(0, l.find('\t')) != key) fprintf(f, "%s\n", l.c_str());
-        fprintf(f, "%s\t%d %d %d %d %d %d %.9f\n", key.c_str(), bt.wave_dmax, bt.wg_blocks_per_cu,
-                bt.wave_blocks_per_cu, bt.queue_chunk_div, bt.wg_dmax, bt.local_bits, bsec);
+        fprintf(f, "%s\t%d %d %d %d %d %d %d %.9f\n", key.c_str(), bt.wave_dmax, bt.wg_blocks_per_cu,
+                bt.wave_blocks_per_cu, bt.queue_chunk_div, bt.wg_dmax, bt.local_bits, bt.wg_waves, bsec);
         fclose(f);
     }
     return KC_OK;

@@ -940,15 +940,16 @@ __host__ __device__ inline size_t wg_local_bytes(int K) {
         default: return wg_local_bytes<10>();
     }
 }
-__host__ __device__ inline size_t wg_static_lds(int K) { return wg_local_bytes(K) * WAVES + 128; }
+// static LDS of the workgroup kernel with nw waves per block
+__host__ __device__ inline size_t wg_static_lds(int K, int nw = WAVES) { return wg_local_bytes(K) * nw + 128; }
 
 // Layout of one workgroup's arena (LDS, or a global slice for the scratch tier)
-// for out-degree cap D and clique size K.
+// for out-degree cap D, clique size K and nw waves per block.
 struct WgLayout {
     size_t nb, seg, colr, delta, stk, htab, bm, bytes;
     uint32_t W, hbits;
 };
-__host__ __device__ inline WgLayout wg_layout(uint32_t D, int K) {
+__host__ __device__ inline WgLayout wg_layout(uint32_t D, int K, int nw = WAVES) {
     WgLayout L;
     const uint32_t W = (D + 63) / 64;
     const int levels = K > 3 ? K - 3 : 1;  // wide depth-first stack entries
@@ -961,11 +962,11 @@ __host__ __device__ inline WgLayout wg_layout(uint32_t D, int K) {
     L.hbits = hash_bits(D);
     // the table lives in the per-wave local-graph areas (idle while staging) when it fits
     const size_t hbytes = ((size_t)1 << L.hbits) * 2;
-    L.htab = hbytes <= wg_local_bytes(K) * WAVES ? (size_t)-1 : o;
+    L.htab = hbytes <= wg_local_bytes(K) * nw ? (size_t)-1 : o;
     if (L.htab != (size_t)-1) o += hbytes;
     o = (o + 7) & ~(size_t)7;
     L.delta = o; o += (size_t)D * 8;
-    L.stk = o;   o += (size_t)WAVES * levels * W * 8;
+    L.stk = o;   o += (size_t)nw * levels * W * 8;
     L.bm = o;    o += tri_words(D) * 8;
     L.bytes = o;
     return L;
@@ -1096,15 +1097,18 @@ __device__ __forceinline__ void wide_edges(const uint64_t *C, uint32_t lo, uint3
     if (cnt) flush(cnt);
 }
 
-template <int K, bool GLOBAL, int MODE>
-__global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
+// NW waves per block (4, 8 or 16): the waves share the root's bitmap, so a larger
+// block keeps more waves resident when one arena fills most of the LDS.
+template <int K, bool GLOBAL, int MODE, int NW>
+__global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
+    constexpr uint32_t WGT = NW * 64;
     extern __shared__ __align__(16) unsigned char smem_dyn[];
-    __shared__ __align__(16) uint64_t s_lraw[WAVES][wg_local_bytes<K>() / 8];
+    __shared__ __align__(16) uint64_t s_lraw[NW][wg_local_bytes<K>() / 8];
     __shared__ uint32_t s_misc[4];
-    __shared__ uint64_t s_red[WAVES];
-    __shared__ int s_ovf[WAVES];
+    __shared__ uint64_t s_red[NW];
+    __shared__ int s_ovf[NW];
     unsigned char *arena = GLOBAL ? (unsigned char *)(p.gscratch + (size_t)blockIdx.x * p.slice_words) : smem_dyn;
-    const WgLayout L = wg_layout(p.dcap, K);
+    const WgLayout L = wg_layout(p.dcap, K, NW);
     uint32_t *nb = (uint32_t *)(arena + L.nb);
     uint32_t *seg = (uint32_t *)(arena + L.seg);
     uint32_t *colr = (uint32_t *)(arena + L.colr);
@@ -1164,17 +1168,17 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
             W = (d + 63) / 64;
             words = tri_words(d);
             const uint64_t *src = p.wbits + p.woff[u];
-            for (uint64_t w = tid; w < words; w += WG) bm[w] = src[w];
+            for (uint64_t w = tid; w < words; w += WGT) bm[w] = src[w];
             if (p.colored) {
-                for (uint32_t t = tid; t < d; t += WG) nb[t] = p.ocol[base + t];
+                for (uint32_t t = tid; t < d; t += WGT) nb[t] = p.ocol[base + t];
                 __syncthreads();
                 if (p.scheme == KC_COLOR_GLOBAL) {
                     // nodes of u's colour; rows of the others and edges to them vanish
                     const uint32_t cu = node_colour(p.seed, p.rank2id[u], p.c);
-                    for (uint32_t t = tid; t < d; t += WG)
+                    for (uint32_t t = tid; t < d; t += WGT)
                         colr[t] = node_colour(p.seed, p.rank2id[nb[t]], p.c) == cu ? 1u : 0u;
                     __syncthreads();
-                    for (uint32_t l = tid; l < W; l += WG) {  // keep mask, word l, as two halves in seg
+                    for (uint32_t l = tid; l < W; l += WGT) {  // keep mask, word l, as two halves in seg
                         uint64_t km = 0;
                         for (uint32_t b = 0; b < 64 && 64 * l + b < d; ++b)
                             if (colr[64 * l + b]) km |= 1ull << b;
@@ -1182,7 +1186,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                         seg[2 * l + 1] = (uint32_t)(km >> 32);
                     }
                     __syncthreads();
-                    for (uint32_t i = tid; i < d; i += WG) {
+                    for (uint32_t i = tid; i < d; i += WGT) {
                         uint64_t *ri = bm + tri_rowoff(i, W) - ((i + 1) >> 6);
                         const bool ki = colr[i] != 0u;
                         for (uint32_t l = (i + 1) >> 6; l < W; ++l)
@@ -1190,10 +1194,10 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                     }
                 } else {
                     // edges whose two ends differ in colour vanish
-                    for (uint32_t t = tid; t < d; t += WG)
+                    for (uint32_t t = tid; t < d; t += WGT)
                         colr[t] = root_colour(p.seed, p.rank2id[u], p.rank2id[nb[t]], p.c);
                     __syncthreads();
-                    for (uint32_t i = tid; i < d; i += WG) {
+                    for (uint32_t i = tid; i < d; i += WGT) {
                         uint64_t *ri = bm + tri_rowoff(i, W) - ((i + 1) >> 6);
                         const uint32_t ci0 = colr[i];
                         for (uint32_t l = (i + 1) >> 6; l < W; ++l) {
@@ -1209,12 +1213,12 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                 }
             }
         } else {
-            for (uint32_t t = tid; t < d; t += WG) nb[t] = p.ocol[base + t];
+            for (uint32_t t = tid; t < d; t += WGT) nb[t] = p.ocol[base + t];
             __syncthreads();
             if (p.colored && p.scheme == KC_COLOR_GLOBAL) {
                 // keep only the nodes of u's colour, preserving order
                 const uint32_t cu = node_colour(p.seed, p.rank2id[u], p.c);
-                for (uint32_t t = tid; t < d; t += WG) seg[t] = node_colour(p.seed, p.rank2id[nb[t]], p.c) == cu ? 1u : 0u;
+                for (uint32_t t = tid; t < d; t += WGT) seg[t] = node_colour(p.seed, p.rank2id[nb[t]], p.c) == cu ? 1u : 0u;
                 __syncthreads();
                 if (tid == 0) {
                     uint32_t w = 0;
@@ -1227,7 +1231,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
             }
             W = (d + 63) / 64;
             // out-degrees of Gamma+(u) and their exclusive prefix
-            for (uint32_t t = tid; t < d; t += WG) {
+            for (uint32_t t = tid; t < d; t += WGT) {
                 const uint32_t x = nb[t];
                 seg[t] = (uint32_t)(p.optr[x + 1] - p.optr[x]);
                 if (p.colored && p.scheme == KC_COLOR_PER_ROOT) colr[t] = root_colour(p.seed, p.rank2id[u], p.rank2id[x], p.c);
@@ -1248,11 +1252,11 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                 if (lane == 0) seg[d] = carry;
             }
             words = tri_words(d);
-            for (uint64_t w = tid; w < words; w += WG) bm[w] = 0;
-            for (uint32_t h = tid; h < hsize / 2; h += WG) reinterpret_cast<uint32_t *>(htab)[h] = HEMPTY;
+            for (uint64_t w = tid; w < words; w += WGT) bm[w] = 0;
+            for (uint32_t h = tid; h < hsize / 2; h += WGT) reinterpret_cast<uint32_t *>(htab)[h] = HEMPTY;
             if (tid == 0) s_misc[3] = 0;
             __syncthreads();
-            for (uint32_t t = tid; t < d; t += WG) hash_insert(htab, hbits, nb[t], t);
+            for (uint32_t t = tid; t < d; t += WGT) hash_insert(htab, hbits, nb[t], t);
             __syncthreads();
             const uint32_t Ttot = seg[d];
             if (d > 0) {
@@ -1280,7 +1284,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
                         }
                     }
                 } else {
-                    for (uint32_t e = tid; e < Ttot; e += WG) {
+                    for (uint32_t e = tid; e < Ttot; e += WGT) {
                         const uint32_t i = seg_find(seg, d, e);
                         const uint32_t y = p.ocol[delta[i] + e];
                         if (y > alast) continue;
@@ -1297,7 +1301,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
             __syncthreads();
             uint64_t *dst = p.wbits + p.woff[u];
             uint32_t ec = 0;
-            for (uint64_t w = tid; w < words; w += WG) {
+            for (uint64_t w = tid; w < words; w += WGT) {
                 dst[w] = bm[w];
                 ec += (uint32_t)__popcll(bm[w]);
             }
@@ -1308,7 +1312,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
             __syncthreads();
             if (tid == 0) {
                 uint64_t e = 0;
-                for (int w = 0; w < WAVES; ++w) e += s_red[w];
+                for (int w = 0; w < NW; ++w) e += s_red[w];
                 if (p.wedges) p.wedges[u] = e > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)e;
                 const uint64_t nt = block_total + e;
                 if (nt < block_total) ovf = 1;
@@ -1323,7 +1327,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
         uint64_t acc = 0;
         if (K == 3 && parts == 1) {
             // q_{u,2} = edges of G+(u) = set bits of the whole bitmap
-            for (uint64_t w = tid; w < words; w += WG) acc += (uint64_t)__popcll(bm[w]);
+            for (uint64_t w = tid; w < words; w += WGT) acc += (uint64_t)__popcll(bm[w]);
         } else {
             // first-level nodes; a root split into `parts` items (Section 7: heavy
             // G+(u) shared by several reducers) takes the nodes part, part + parts,
@@ -1533,7 +1537,7 @@ __global__ void __launch_bounds__(WG) k_count_wg(CountParams p) {
         __syncthreads();
         if (tid == 0) {
             uint64_t q = 0;
-            for (int w = 0; w < WAVES; ++w) {
+            for (int w = 0; w < NW; ++w) {
                 const uint64_t nq = q + s_red[w];
                 if (nq < q || s_ovf[w]) ovf = 1;
                 q = nq;
@@ -1638,30 +1642,63 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
         p.gscratch = gscratch;
         p.slice_words = slice_words;
         p.dcap = q.max_d[2];
-        hipLaunchKernelGGL((k_count_wg<K, true, MODE>), dim3(scratch_blocks), dim3(WG), 0, s, p);
+        hipLaunchKernelGGL((k_count_wg<K, true, MODE, WAVES>), dim3(scratch_blocks), dim3(WG), 0, s, p);
     }
     if (ev) (void)hipEventRecord(ev[1], s);
     if (q.count[1]) {
-        // the attribute only caps the dynamic LDS of later launches (graph replays included)
-        (void)hipFuncSetAttribute((const void *)&k_count_wg<K, false, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(di.lds_max - wg_static_lds(K)));
-        // resident blocks per CU for an arena sized for out-degree dmax
-        auto blocks_per_cu = [&](uint32_t dmax) {
-            const WgLayout L = wg_layout(dmax < 65 ? 65 : dmax, K);
-            const size_t per_block = L.bytes + wg_static_lds(K) + 256;
-            uint32_t per_cu = (uint32_t)(di.lds_max / per_block);
-            // and no more than are resident at once (registers): a block launched past
-            // that starts only when the queue is spent
-            int occ = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)&k_count_wg<K, false, MODE>, WG,
-                                                             L.bytes) == hipSuccess &&
-                occ > 0 && (uint32_t)occ < per_cu)
-                per_cu = (uint32_t)occ;
-            if (per_cu < 1) per_cu = 1;
-            if (per_cu > 8) per_cu = 8;
-            if (tu.wg_blocks_per_cu > 0 && (uint32_t)tu.wg_blocks_per_cu < per_cu)
-                per_cu = (uint32_t)tu.wg_blocks_per_cu;
-            return per_cu;
+        // Block shape of a launch whose arena holds out-degree dmax: waves per block
+        // (4, 8 or 16; the wg_waves tunable fixes it) and resident blocks per CU.  Four
+        // waves per block while at least two such blocks fit on a CU (the waves of a
+        // block share one root or item: small blocks balance better); otherwise the
+        // shape with the most waves resident (LDS and registers), at most 32.  One
+        // large arena per block (a root of out-degree 1031 takes about 90 KB) leaves
+        // room for one block: more waves in it keep the CU busy while others wait on
+        // LDS.  Measured: R-MAT 22 at k = 5, 1.98 s with four waves, 1.44 s with the
+        // larger block; planted 4M at k = 8, 349 ms with two four-wave blocks per CU,
+        // 570 ms with one 16-wave block.
+        const void *fn[3] = {(const void *)&k_count_wg<K, false, MODE, 4>, (const void *)&k_count_wg<K, false, MODE, 8>,
+                             (const void *)&k_count_wg<K, false, MODE, 16>};
+        const int nws[3] = {4, 8, 16};
+        // static LDS of each block shape as compiled (the per-wave arrays grow with it),
+        // looked up once; the attribute caps the dynamic LDS of later launches (graph
+        // replays included)
+        static size_t stat[3] = {0, 0, 0};
+        for (int i = 0; i < 3; ++i) {
+            if (!stat[i]) {
+                hipFuncAttributes fa;
+                stat[i] = hipFuncGetAttributes(&fa, fn[i]) == hipSuccess ? fa.sharedSizeBytes
+                                                                          : wg_static_lds(K, nws[i]) + 1024;
+            }
+            if (stat[i] < di.lds_max)
+                (void)hipFuncSetAttribute(fn[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)(di.lds_max - stat[i]));
+        }
+        struct Shape {
+            int idx;
+            uint32_t per_cu;
+        };
+        auto shape = [&](uint32_t dmax) {
+            Shape best{0, 0};
+            for (int i = 0; i < 3; ++i) {
+                const int nw = nws[i];
+                if (tu.wg_waves && tu.wg_waves != nw) continue;
+                const WgLayout L = wg_layout(dmax < 65 ? 65 : dmax, K, nw);
+                const size_t per_block = L.bytes + stat[i] + 256;
+                if (per_block > di.lds_max) continue;
+                uint32_t per_cu = (uint32_t)(di.lds_max / per_block);
+                // no more than are resident at once (registers): a block launched past
+                // that starts only when the queue is spent
+                int occ = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn[i], nw * 64, L.bytes) == hipSuccess && occ > 0 &&
+                    (uint32_t)occ < per_cu)
+                    per_cu = (uint32_t)occ;
+                if (per_cu * (uint32_t)nw > 32u) per_cu = 32u / (uint32_t)nw;
+                if (tu.wg_blocks_per_cu > 0 && (uint32_t)tu.wg_blocks_per_cu < per_cu)
+                    per_cu = (uint32_t)tu.wg_blocks_per_cu;
+                if (i == 0 && per_cu >= 2 && !tu.wg_waves) return Shape{0, per_cu};
+                if (per_cu * (uint32_t)nw > best.per_cu * (uint32_t)nws[best.idx]) best = Shape{i, per_cu};
+            }
+            if (best.per_cu == 0) best = Shape{0, 1};  // every root of the tier fits four waves' arena
+            return best;
         };
         auto launch_wg = [&](const uint32_t *queue, uint32_t count, const uint64_t *items, uint32_t *next,
                              uint32_t dmax) {
@@ -1671,10 +1708,17 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
             p.items = items;
             p.next = next;
             p.dcap = dmax < 65 ? 65 : dmax;
-            const WgLayout L = wg_layout(p.dcap, K);
-            uint32_t blocks = (uint32_t)di.cus * blocks_per_cu(dmax);
+            const Shape sh = shape(dmax);
+            const int nw = nws[sh.idx];
+            const WgLayout L = wg_layout(p.dcap, K, nw);
+            uint32_t blocks = (uint32_t)di.cus * sh.per_cu;
             if (blocks > count) blocks = count;
-            hipLaunchKernelGGL((k_count_wg<K, false, MODE>), dim3(blocks), dim3(WG), L.bytes, s, p);
+            if (nw == 16)
+                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 16>), dim3(blocks), dim3(1024), L.bytes, s, p);
+            else if (nw == 8)
+                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 8>), dim3(blocks), dim3(512), L.bytes, s, p);
+            else
+                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 4>), dim3(blocks), dim3(256), L.bytes, s, p);
         };
         if (q.wg_items) {
             launch_wg(q.ptr[1], q.wg_item_count, q.wg_items, cursors + 1, q.max_d[1]);
@@ -1683,11 +1727,12 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
             // class joins the current group when a launch of its own would hold no
             // more blocks per CU, or when the group is too short to keep the device
             // busy past its tail (fewer than 4 roots per resident block).
-            uint32_t g0 = 0, cnt = q.wg_cls_cnt[0], cap = blocks_per_cu(q.wg_cls_dmax[0]);
+            Shape cap = shape(q.wg_cls_dmax[0]);
+            uint32_t g0 = 0, cnt = q.wg_cls_cnt[0];
             for (uint32_t c = 1; c <= q.wg_ncls; ++c) {
                 if (c < q.wg_ncls) {
-                    const uint32_t pc = blocks_per_cu(q.wg_cls_dmax[c]);
-                    if (pc == cap || cnt < 4u * (uint32_t)di.cus * cap) {
+                    const Shape sc = shape(q.wg_cls_dmax[c]);
+                    if ((sc.idx == cap.idx && sc.per_cu == cap.per_cu) || cnt < 4u * (uint32_t)di.cus * cap.per_cu) {
                         cnt += q.wg_cls_cnt[c];
                         continue;
                     }
@@ -1696,7 +1741,7 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
                 if (c < q.wg_ncls) {
                     g0 = c;
                     cnt = q.wg_cls_cnt[c];
-                    cap = blocks_per_cu(q.wg_cls_dmax[c]);
+                    cap = shape(q.wg_cls_dmax[c]);
                 }
             }
         } else {

@@ -78,11 +78,24 @@ struct kc_graph {
     uint32_t max_outdeg = 0;
 
     // schedule
-    int policy = KC_SCHED_DEGREE;
+    int policy = KC_SCHED_EDGES;
     float *mlp = nullptr;   // device weights (KC_MLP_PARAMS floats + normalisation)
     int mlp_loaded = 0;
     uint64_t *tri = nullptr;  // per-root edges of G+(u) by original id (scheduler feature), cached
     float *feat = nullptr;    // scheduler features that do not depend on k, cached (rank order)
+    uint32_t feat_upto = 0;   // features are valid for the first feat_upto roots of the degree queue
+    int feat_dqwd = -1;       // ... built with this wave-tier limit
+    uint64_t mlp_serial = 0;  // bumped on every weight load
+    // learned queue of each clique size, built once per (weights, tier limits)
+    struct LearnedQueue {
+        int ready = 0, wd = 0;
+        uint32_t dcap = 0;
+        uint64_t wserial = 0;
+        uint32_t *queue = nullptr;   // scratch, workgroup, one-wave tier (with the degree queue's tail)
+        uint64_t *items = nullptr;   // workgroup tier as split items (k >= 5)
+        uint32_t item_count = 0;
+        uint32_t count[3] = {0, 0, 0}, max_d[3] = {0, 0, 0};  // kc_queue order: wave, workgroup, scratch
+    } lq[KC_KMAX + 1];
 
     // small result area on the device: [0] total, [1] overflow flag, [2..] cursors
     uint64_t *d_res = nullptr;
@@ -185,6 +198,7 @@ struct kc_tuning_t {
     int chunk_div = 8;           // queue chunk = roots / (workers * chunk_div), 1..64
     int wg_dmax = 0;             // workgroup-tier out-degree limit (0: as LDS allows); larger roots go to scratch
     int local_bits = 128;        // widest local graph candidate sets are compacted into (64 or 128 nodes)
+    int wg_waves = 0;            // waves per workgroup-tier block (0: chosen per launch)
 };
 const kc_tuning_t &kc_tuning_now();
 
@@ -194,7 +208,8 @@ const kc_tuning_t &kc_tuning_now();
 #define KC_RES_SLOTS 1040  // first of the 32 partial-total words (summed into word 0 at the end)
 #define KC_MLP_IN 8
 #define KC_MLP_H 32
-#define KC_MLP_PARAMS (KC_MLP_IN * KC_MLP_H + KC_MLP_H + KC_MLP_H * KC_MLP_H + KC_MLP_H + KC_MLP_H + 1)
+static_assert(KC_MLP_PARAMS == KC_MLP_IN * KC_MLP_H + KC_MLP_H + KC_MLP_H * KC_MLP_H + KC_MLP_H + KC_MLP_H + 1,
+              "KC_MLP_PARAMS of kc.h");
 struct kc_queue {
     kc_tmp buf;                // storage when the queue is built per call
     kc_tmp items_buf;
@@ -214,7 +229,17 @@ struct kc_queue {
 kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_max, kc_queue &q,
                          bool no_alloc = false);
 size_t kc_scratch_slice_words(uint32_t dmax, int k);
-kc_status kc_features(const kc_graph *g, float *d_feat, hipStream_t s);
+// Inference and queue keys of the learned policy for the candidate roots dq[0, C)
+// (kc_mlp.hip; key layout in kc_learned_prio below).
+kc_status kc_learned_keys(const kc_graph *g, int k, uint32_t C, uint32_t wd, uint32_t dcap, float promote,
+                          uint64_t *keys, uint32_t *stats, hipStream_t s);
+// 24-bit queue priority of a predicted log-work (2^-18 steps, larger work first) and back
+__host__ __device__ inline uint32_t kc_learned_prio(float logwork) {
+    float v = logwork * 262144.0f;
+    v = v < 0.f ? 0.f : (v > 16777215.f ? 16777215.f : v);
+    return 0xFFFFFFu - (uint32_t)v;
+}
+__host__ __device__ inline double kc_learned_logwork(uint32_t prio) { return (double)(0xFFFFFFu - prio) / 262144.0; }
 
 // ----------------------------------------------------------------------------
 // Wave64 helpers

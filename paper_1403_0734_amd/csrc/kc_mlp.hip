@@ -44,10 +44,9 @@ __device__ __forceinline__ double log_cliques(uint32_t d, double dens, int k) {
     return lc;
 }
 
-__global__ void k_features(const uint64_t *optr, const uint32_t *ocol, const uint32_t *rank2id, const uint32_t *deg,
-                           const uint64_t *tri_by_id, uint32_t n, int k, float *feat) {
-    const size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n) return;
+// The eight features of root u (rank space) for clique size k; ep = edges of G+(u).
+__device__ __forceinline__ void root_features(uint32_t u, const uint64_t *optr, const uint32_t *ocol, uint32_t deg_u,
+                                              double ep, int k, float *f) {
     const uint64_t b = optr[u], e = optr[u + 1];
     const uint32_t d = (uint32_t)(e - b);
     double wedges = 0.0;
@@ -58,20 +57,47 @@ __global__ void k_features(const uint64_t *optr, const uint32_t *ocol, const uin
         wedges += dx;
         mx = dx > mx ? dx : mx;
     }
-    const uint32_t id = rank2id[u];
-    const double ep = (double)tri_by_id[id];
     const double pairs = d >= 2 ? 0.5 * (double)d * (double)(d - 1) : 0.0;
     const double dens = pairs > 0 ? ep / pairs : 0.0;
     const double lc = log_cliques(d, dens, k);
-    float *f = feat + u * NF;
     f[0] = (float)log1p((double)d);
     f[1] = (float)log1p(wedges);
     f[2] = (float)log1p((double)mx);
-    f[3] = (float)log1p((double)deg[id]);
+    f[3] = (float)log1p((double)deg_u);
     f[4] = (float)log1p(ep);
     f[5] = (float)dens;
     f[6] = (float)k / 10.0f;
     f[7] = (float)lc;
+}
+
+// every root, edges of G+(u) from the per-root k = 3 counts (by original id)
+__global__ void k_features(const uint64_t *optr, const uint32_t *ocol, const uint32_t *rank2id, const uint32_t *deg,
+                           const uint64_t *tri_by_id, uint32_t n, int k, float *feat) {
+    const size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    const uint32_t id = rank2id[u];
+    root_features((uint32_t)u, optr, ocol, deg[id], (double)tri_by_id[id], k, feat + u * NF);
+}
+
+// roots list[lo, hi) (ranks), edges of G+(u) from the staged cache: the bitmap's edge
+// count for roots above the one-wave limit, the popcounts of the staged rows below it
+__global__ void k_features_list(const uint32_t *list, uint32_t lo, uint32_t hi, const uint64_t *optr,
+                                const uint32_t *ocol, const uint32_t *rank2id, const uint32_t *deg,
+                                const uint64_t *lrows, const uint32_t *wedges, uint32_t stage_wd, float *feat) {
+    const size_t i = lo + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= hi) return;
+    const uint32_t u = list[i];
+    const uint64_t b = optr[u];
+    const uint32_t d = (uint32_t)(optr[u + 1] - b);
+    double ep = 0.0;
+    if (d > stage_wd) {
+        ep = (double)wedges[u];
+    } else if (d >= 2) {  // roots of out-degree 0 and 1 are never staged
+        uint64_t c = 0;
+        for (uint32_t j = 0; j < d; ++j) c += (uint64_t)__popcll(lrows[b + j]);
+        ep = (double)c;
+    }
+    root_features(u, optr, ocol, deg[rank2id[u]], ep, 4, feat + (size_t)u * NF);
 }
 
 __device__ __forceinline__ float mlp_forward(const float *P, const float *x, float *h1, float *z1, float *h2,
@@ -119,8 +145,58 @@ __global__ void __launch_bounds__(T) k_mlp_infer_k(const float *feat, uint32_t n
     pred[u] = y * norm[2 * NF + 1] + norm[2 * NF];
 }
 
+// Learned queue of one clique size: inference for the candidate roots dq[0, C) and
+// their sort keys, tier (0 scratch, 1 workgroup, 2 one-wave) | 24-bit complement of
+// the predicted log-work | rank.  One-wave roots whose predicted log-work reaches
+// `promote` move to the workgroup tier.  stats: [0..2] roots per tier, [4..6] the
+// largest out-degree per tier.
+__global__ void __launch_bounds__(T) k_learned_cand(const uint32_t *dq, uint32_t C, const float *feat, int k,
+                                                    const uint64_t *optr, const float *params, uint32_t wd,
+                                                    uint32_t dcap, float promote, uint64_t *keys, uint32_t *stats) {
+    __shared__ float P[NP + NORM];
+    __shared__ uint32_t s_c[3], s_m[3];
+    for (int i = threadIdx.x; i < NP + NORM; i += blockDim.x) P[i] = params[i];
+    if (threadIdx.x < 3) s_c[threadIdx.x] = s_m[threadIdx.x] = 0;
+    __syncthreads();
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t tier = 3, d = 0;
+    if (i < C) {
+        const uint32_t u = dq[i];
+        d = (uint32_t)(optr[u + 1] - optr[u]);
+        tier = d > dcap ? 0u : (d > wd ? 1u : 2u);
+        const float *norm = P + NP;
+        float f[NF], x[NF], h1[H], z1[H], h2[H], z2[H];
+#pragma unroll
+        for (int j = 0; j < NF; ++j) f[j] = feat[(size_t)u * NF + j];
+        f[6] = (float)k / 10.0f;
+        f[7] = (float)log_cliques(d, (double)f[5], k);
+#pragma unroll
+        for (int j = 0; j < NF; ++j) x[j] = (f[j] - norm[j]) / norm[NF + j];
+        const float w = mlp_forward(P, x, h1, z1, h2, z2) * norm[2 * NF + 1] + norm[2 * NF];
+        if (tier == 2 && w >= promote) tier = 1;
+        keys[i] = ((uint64_t)tier << 62) | ((uint64_t)kc_learned_prio(w) << 32) | (uint64_t)u;
+    }
+#pragma unroll
+    for (uint32_t t = 0; t < 3; ++t) {
+        const bool in = tier == t;
+        const uint32_t c = (uint32_t)__popcll(__ballot(in));
+        const uint32_t m = kc_wave_max_u32(in ? d : 0u);
+        if ((threadIdx.x & 63) == 0 && c) {
+            atomicAdd(&s_c[t], c);
+            atomicMax(&s_m[t], m);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3 && s_c[threadIdx.x]) {
+        atomicAdd(&stats[threadIdx.x], s_c[threadIdx.x]);
+        atomicMax(&stats[4 + threadIdx.x], s_m[threadIdx.x]);
+    }
+}
+
 // One mini-batch gradient: 64 samples per block (one wave), per-block sums of the
-// parameter gradients of 0.5 * mean (y - t)^2, added to grad with atomics.
+// parameter gradients of 0.5 * mean (y - t)^2, added to grad with atomics.  Sample s
+// of the batch is row order[start + s] of X (row start + s without an order);
+// loss += sum of 0.5 (y - t)^2 over the batch.
 constexpr int GB = 64;
 __global__ void __launch_bounds__(GB) k_mlp_grad(const float *X, const float *Tg, const uint32_t *order, size_t start,
                                                  size_t count, const float *params, float *grad, float *loss) {
@@ -133,13 +209,13 @@ __global__ void __launch_bounds__(GB) k_mlp_grad(const float *X, const float *Tg
     float x[NF], h1[H], z1[H], h2[H], z2[H];
     float dy = 0.f;
     if (s < count) {
-        const size_t idx = order[start + s];
+        const size_t idx = order ? (size_t)order[start + s] : start + s;
 #pragma unroll
         for (int i = 0; i < NF; ++i) x[i] = X[idx * NF + i];
         const float y = mlp_forward(P, x, h1, z1, h2, z2);
         const float err = y - Tg[idx];
         dy = err / (float)count;
-        atomicAdd(loss, 0.5f * err * err / (float)count);
+        atomicAdd(loss, 0.5f * err * err);
     } else {
 #pragma unroll
         for (int i = 0; i < NF; ++i) x[i] = 0.f;
@@ -248,24 +324,122 @@ kc_status features(const kc_graph *g, int k, float *feat, hipStream_t s) {
 
 }  // namespace
 
-kc_status kc_predict_work(const kc_graph *g, int k, float *d_pred, hipStream_t s) {
-    if (!g->mlp_loaded) return kc_fail(KC_ESTATE, "no scheduler weights loaded");
+// Features of the first `upto` roots of the degree queue, kept on the handle
+// (rank order): from the staged cache when it is kept, else from per-root k = 3
+// counts.  Later calls compute only the roots past the cached prefix.
+static kc_status features_prefix(const kc_graph *g, uint32_t upto, hipStream_t s) {
     kc_graph *gm = const_cast<kc_graph *>(g);
-    if (!gm->feat) {  // the k-independent features, once per graph
-        KC_TRY(kc_dev_alloc((void **)&gm->feat, (size_t)g->n * NF * 4, s));
-        KC_TRY(features(g, 4, gm->feat, s));
+    if (gm->feat_dqwd != g->dq_wd) gm->feat_upto = 0;
+    if (upto <= gm->feat_upto) return KC_OK;
+    if (!gm->feat) KC_TRY(kc_dev_alloc((void **)&gm->feat, (size_t)g->n * NF * 4, s));
+    const bool cached = g->staged == 1 && g->stage_wd == g->dq_wd && g->wedges && g->lrows;
+    if (cached) {
+        const uint32_t lo = gm->feat_upto;
+        hipLaunchKernelGGL(k_features_list, dim3(grid_for(upto - lo)), dim3(T), 0, s, (const uint32_t *)g->dq, lo,
+                           upto, (const uint64_t *)g->optr, (const uint32_t *)g->ocol, (const uint32_t *)g->rank2id,
+                           (const uint32_t *)g->deg, (const uint64_t *)g->lrows, (const uint32_t *)g->wedges,
+                           (uint32_t)g->stage_wd, gm->feat);
+        KC_HIP(hipGetLastError());
+        gm->feat_upto = upto;
+    } else {
+        KC_TRY(features(g, 4, gm->feat, s));  // every root
+        gm->feat_upto = 0xFFFFFFFFu;
     }
-    hipLaunchKernelGGL(k_mlp_infer_k, dim3(grid_for(g->n)), dim3(T), 0, s, (const float *)gm->feat, g->n, k,
-                       (const uint64_t *)g->optr, (const float *)g->mlp, d_pred);
+    gm->feat_dqwd = g->dq_wd;
+    return KC_OK;
+}
+
+kc_status kc_learned_keys(const kc_graph *g, int k, uint32_t C, uint32_t wd, uint32_t dcap, float promote,
+                          uint64_t *keys, uint32_t *stats, hipStream_t s) {
+    if (!g->mlp_loaded) return kc_fail(KC_ESTATE, "no scheduler weights loaded");
+    if (C == 0) return KC_OK;
+    KC_TRY(features_prefix(g, C, s));
+    hipLaunchKernelGGL(k_learned_cand, dim3(grid_for(C)), dim3(T), 0, s, (const uint32_t *)g->dq, C,
+                       (const float *)g->feat, k, (const uint64_t *)g->optr, (const float *)g->mlp, wd, dcap, promote,
+                       keys, stats);
     KC_HIP(hipGetLastError());
     return KC_OK;
 }
 
-kc_status kc_features(const kc_graph *g, float *d_feat, hipStream_t s) { return features(g, 4, d_feat, s); }
+namespace {
+// predictions of every root at clique size k, written by original id
+__global__ void k_predict_by_id(const float *feat, uint32_t n, int k, const uint64_t *optr, const uint32_t *rank2id,
+                                const float *params, float *pred, float *feat_out) {
+    __shared__ float P[NP + NORM];
+    for (int i = threadIdx.x; i < NP + NORM; i += blockDim.x) P[i] = params[i];
+    __syncthreads();
+    const size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    const uint32_t d = (uint32_t)(optr[u + 1] - optr[u]);
+    const uint32_t id = rank2id[u];
+    const float *norm = P + NP;
+    float f[NF], x[NF], h1[H], z1[H], h2[H], z2[H];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) f[i] = feat[u * NF + i];
+    f[6] = (float)k / 10.0f;
+    f[7] = (float)log_cliques(d, (double)f[5], k);
+    if (feat_out) {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) feat_out[(size_t)id * NF + i] = f[i];
+    }
+    if (d < (uint32_t)(k - 1)) {
+        pred[id] = 0.f;
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i) x[i] = (f[i] - norm[i]) / norm[NF + i];
+    pred[id] = mlp_forward(P, x, h1, z1, h2, z2) * norm[2 * NF + 1] + norm[2 * NF];
+}
+}  // namespace
+
+extern "C" kc_status kc_predict_work(const kc_graph *g, int32_t k, float *dev_pred, float *dev_feat) {
+    if (!g) return kc_fail(KC_EINVAL, "graph is NULL");
+    if (!dev_pred) return kc_fail(KC_EINVAL, "dev_pred is NULL");
+    if (k < 3 || k > KC_KMAX) return kc_fail(KC_EINVAL, "k=%d outside [3, %d]", k, KC_KMAX);
+    if (!g->oriented) return kc_fail(KC_ESTATE, "kc_orient has not been called");
+    if (!g->mlp_loaded) return kc_fail(KC_ESTATE, "no scheduler weights loaded");
+    hipStream_t s = g->stream;
+    kc_tmp feat;
+    KC_TRY(kc_tmp_alloc(feat, (size_t)g->n * NF * 4, s));
+    KC_TRY(features(g, 4, feat.as<float>(), s));
+    hipLaunchKernelGGL(k_predict_by_id, dim3(grid_for(g->n)), dim3(T), 0, s, (const float *)feat.as<float>(), g->n, k,
+                       (const uint64_t *)g->optr, (const uint32_t *)g->rank2id, (const float *)g->mlp, dev_pred,
+                       dev_feat);
+    KC_HIP(hipGetLastError());
+    KC_TRY(kc_sync(s));
+    return KC_OK;
+}
+
+extern "C" kc_status kc_mlp_step(float *dev_params, float *dev_adam_m, float *dev_adam_v, int32_t step, float lr,
+                                 const float *dev_x, const float *dev_t, uint32_t count, float *dev_grad, float *loss,
+                                 void *hip_stream) {
+    if (!dev_params || !dev_adam_m || !dev_adam_v || !dev_x || !dev_t) return kc_fail(KC_EINVAL, "NULL argument");
+    if (count == 0) return kc_fail(KC_EINVAL, "count must be positive");
+    if (step < 1) return kc_fail(KC_EINVAL, "step must be at least 1");
+    if (!(lr > 0.f) || lr != lr || lr > 1e30f) return kc_fail(KC_EINVAL, "lr must be positive and finite");
+    hipStream_t s = (hipStream_t)hip_stream;
+    kc_tmp grad, lsum;
+    KC_TRY(kc_tmp_alloc(grad, NP * 4, s));
+    KC_TRY(kc_tmp_alloc(lsum, 4, s));
+    KC_HIP(hipMemsetAsync(grad.p, 0, NP * 4, s));
+    KC_HIP(hipMemsetAsync(lsum.p, 0, 4, s));
+    hipLaunchKernelGGL(k_mlp_grad, dim3((count + GB - 1) / GB), dim3(GB), 0, s, dev_x, dev_t, (const uint32_t *)nullptr,
+                       (size_t)0, (size_t)count, (const float *)dev_params, grad.as<float>(), lsum.as<float>());
+    if (dev_grad) KC_HIP(hipMemcpyAsync(dev_grad, grad.p, NP * 4, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_adam, dim3(1), dim3(256), 0, s, dev_params, grad.as<float>(), dev_adam_m, dev_adam_v, step,
+                       lr);
+    KC_HIP(hipGetLastError());
+    float *h = (float *)kc_pinned_scratch();
+    if (loss) KC_HIP(hipMemcpyAsync(h, lsum.p, 4, hipMemcpyDeviceToHost, s));
+    KC_TRY(kc_sync(s));
+    if (loss) *loss = h[0] / (float)count;
+    return KC_OK;
+}
 
 extern "C" kc_status kc_set_schedule(kc_graph *g, int32_t policy, const char *weights_path) {
     if (!g) return kc_fail(KC_EINVAL, "graph is NULL");
-    if (policy != KC_SCHED_DEGREE && policy != KC_SCHED_LEARNED) return kc_fail(KC_EINVAL, "unknown policy %d", policy);
+    if (policy != KC_SCHED_DEGREE && policy != KC_SCHED_LEARNED && policy != KC_SCHED_EDGES)
+        return kc_fail(KC_EINVAL, "unknown policy %d", policy);
     if (policy == KC_SCHED_LEARNED && weights_path) {
         FILE *f = fopen(weights_path, "rb");
         if (!f) return kc_fail(KC_EINVAL, "cannot open %s", weights_path);
@@ -281,6 +455,7 @@ extern "C" kc_status kc_set_schedule(kc_graph *g, int32_t policy, const char *we
         KC_HIP(hipMemcpyAsync(g->mlp, buf.data(), (NP + NORM) * 4, hipMemcpyHostToDevice, g->stream));
         KC_TRY(kc_sync(g->stream));
         g->mlp_loaded = 1;
+        ++g->mlp_serial;  // learned queues built with other weights are stale
     }
     if (policy == KC_SCHED_LEARNED && !g->mlp_loaded) return kc_fail(KC_ESTATE, "no scheduler weights loaded");
     g->policy = policy;
@@ -415,7 +590,7 @@ extern "C" kc_status kc_train_schedule(kc_graph *const *gs, uint32_t num, int32_
         KC_HIP(hipGetLastError());
         KC_HIP(hipMemcpyAsync(&loss, dL.p, 4, hipMemcpyDeviceToHost, s));
         KC_TRY(kc_sync(s));
-        loss = loss * (float)B / (float)N;  // mean over batches of the batch-mean loss, roughly
+        loss /= (float)N;  // mean over the epoch's samples of 0.5 (y - t)^2, each at its batch's parameters
     }
     KC_HIP(hipMemcpyAsync(hp.data(), dP.p, NP * 4, hipMemcpyDeviceToHost, s));
     KC_TRY(kc_sync(s));

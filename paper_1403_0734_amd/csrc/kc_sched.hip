@@ -5,12 +5,19 @@
 // resources (Section 7).  Here every root u with |Gamma+(u)| >= k-1 (smaller
 // roots hold no (k-1)-clique: the Reduce-1 filter of Algorithm 1) is placed in
 // a tier and the queue of each tier is ordered heaviest first:
-//   degree policy   tier by out-degree, order by out-degree.  The order does not
-//                   depend on k, so the queue is sorted once per graph; for a
-//                   given k the tiers are prefixes read off an out-degree
-//                   histogram (the narrow part stops at out-degree k-1).
-//   learned policy  order (and promotion of small but dense roots to the
-//                   workgroup tier) by an MLP's predicted log-work, per call.
+//   degree policy    tier by out-degree, order by out-degree, whole roots.  The
+//                    order does not depend on k, so the queue is sorted once per
+//                    graph; for a given k the tiers are prefixes read off an
+//                    out-degree histogram (the one-wave part stops at k-1).
+//   edges policy     the degree queue, but from k = 5 the workgroup tier becomes
+//                    items ordered and split by an estimate from the edges of
+//                    G+(u) (known once staged; by out-degree without the cache).
+//   learned policy   from k = 5 the workgroup tier's items ordered and split by
+//                    an MLP's predicted work, and one-wave roots whose predicted
+//                    work is large promoted to the workgroup tier; built once per
+//                    clique size and weights.  Below k = 5 no one-wave root can
+//                    reach the promotion threshold and the queue is the degree
+//                    queue.
 #include <string.h>
 
 #include "kc_internal.h"
@@ -41,48 +48,6 @@ __global__ void k_degree_keys(const uint64_t *optr, uint32_t n, uint32_t wd, uin
         if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
 }
 
-__device__ __forceinline__ void tier_stats(bool active, uint32_t tier, uint32_t d, uint32_t *cnt, uint32_t *mx) {
-    __shared__ uint32_t s_c[3], s_m[3];
-    if (threadIdx.x < 3) s_c[threadIdx.x] = s_m[threadIdx.x] = 0;
-    __syncthreads();
-#pragma unroll
-    for (uint32_t t = 0; t < 3; ++t) {
-        const bool in = active && tier == t;
-        const uint32_t c = (uint32_t)__popcll(__ballot(in));
-        const uint32_t m = kc_wave_max_u32(in ? d : 0u);
-        if ((threadIdx.x & 63) == 0 && c) {
-            atomicAdd(&s_c[t], c);
-            atomicMax(&s_m[t], m);
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < 3 && s_c[threadIdx.x]) {
-        atomicAdd(&cnt[threadIdx.x], s_c[threadIdx.x]);
-        atomicMax(&mx[threadIdx.x], s_m[threadIdx.x]);
-    }
-}
-
-// learned policy: key = tier | descending predicted log-work | rank
-__global__ void k_learned_keys(const uint64_t *optr, uint32_t n, int k, uint32_t wd, uint32_t dcap, const float *pred,
-                               float promote, uint64_t *keys, uint32_t *flag, uint32_t *cnt, uint32_t *mx) {
-    const size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool active = false;
-    uint32_t tier = 0, d = 0;
-    if (u < n) {
-        d = (uint32_t)(optr[u + 1] - optr[u]);
-        active = d >= (uint32_t)(k - 1);
-        tier = d <= wd ? 0u : (d <= dcap ? 1u : 2u);
-        const float w = pred[u];
-        if (tier == 0 && w >= promote) tier = 1;
-        float s = w * 262144.0f;  // log-work in 2^-18 steps
-        s = s < 0.f ? 0.f : (s > 16777215.f ? 16777215.f : s);
-        const uint32_t prio = 0xFFFFFFu - (uint32_t)s;
-        keys[u] = ((uint64_t)tier << 62) | ((uint64_t)prio << 32) | (uint64_t)u;
-        flag[u] = active ? 1u : 0u;
-    }
-    tier_stats(active, tier, d, cnt, mx);
-}
-
 __global__ void k_compact_keys(const uint64_t *keys, const uint32_t *flag, const uint32_t *pos, uint32_t n,
                                uint64_t *out) {
     const size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -92,27 +57,6 @@ __global__ void k_compact_keys(const uint64_t *keys, const uint32_t *flag, const
 __global__ void k_queue_from_keys(const uint64_t *keys, uint32_t cnt, uint32_t *queue) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < cnt) queue[i] = (uint32_t)keys[i];
-}
-
-// Split of the workgroup tier (learned policy): a root whose predicted work w is
-// above `target` is cut into ceil(w / target) items (at most smax); item p takes
-// the first-level nodes p, p + parts, ...
-__global__ void k_work_sum(const uint32_t *q, uint32_t cnt, const float *pred, double *sum) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double w = i < cnt ? expm1((double)pred[q[i]]) : 0.0;
-    for (int off = 32; off >= 1; off >>= 1) w += __shfl_xor(w, off, 64);
-    if ((threadIdx.x & 63) == 0 && w != 0.0) atomicAdd(sum, w);
-}
-
-__global__ void k_split_parts(const uint32_t *q, uint32_t cnt, const float *pred, const double *sum, double per,
-                              uint32_t smax, uint32_t *parts) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cnt) return;
-    const double target = *sum / per > 1.0 ? *sum / per : 1.0;
-    const double w = expm1((double)pred[q[i]]);
-    double np = ceil(w / target);
-    np = np < 1.0 ? 1.0 : (np > (double)smax ? (double)smax : np);
-    parts[i] = (uint32_t)np;
 }
 
 __global__ void k_split_emit(const uint32_t *q, uint32_t cnt, const uint32_t *parts, const uint32_t *off,
@@ -140,10 +84,8 @@ __global__ void k_degree_parts(const uint32_t *q, uint32_t cnt, const uint64_t *
     parts[i] = degree_parts(optr[u + 1] - optr[u], dsplit, sh);
 }
 
-// Work items of the workgroup tier (staged handles), three grid passes and no
-// host round trip:
-//   1. the sum of the roots' estimated work (root_est, from the edges of G+(u)
-//      kept when staging);
+// Work items of the workgroup tier, three grid passes and no host round trip:
+//   1. the sum of the roots' estimated work;
 //   2. items per root, ceil(est / target) with target the smaller of four times
 //      the mean and 1/1024 of the total (at least 1), at most min(64, out-degree);
 //      items per 8-bit estimate bucket;
@@ -151,6 +93,9 @@ __global__ void k_degree_parts(const uint32_t *q, uint32_t cnt, const uint64_t *
 //      longest-processing-time order at bucket resolution), the list padded to
 //      its bound with skipped items.
 // Items: sum of parts <= cnt + total / target <= cnt + max(cnt / 4, 1024).
+// The estimate is either the edge estimate below (KC_SCHED_EDGES, from the edges
+// of G+(u) kept when staging) or the MLP's predicted work (KC_SCHED_LEARNED):
+// the same machinery, only the per-root estimate differs.
 struct WqAux {
     double sum;
     uint32_t bcnt[256];  // items per bucket
@@ -173,22 +118,42 @@ __device__ __forceinline__ uint32_t root_est(uint32_t c, uint64_t d) {
     const double e = 64.0 * (double)c * sqrt((double)c) / (dd * dd);
     return e >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)e;
 }
-__device__ __forceinline__ uint32_t est_of(const uint32_t *q, size_t i, const uint32_t *wedges, const uint64_t *optr) {
-    const uint32_t u = q[i];
-    return root_est(wedges[u], optr[u + 1] - optr[u]);
-}
 
-__global__ void k_edge_sum(const uint32_t *q, uint32_t cnt, const uint32_t *wedges, const uint64_t *optr,
-                           WqAux *a) {
+// Root i of a tier with its edge estimate (queue of ranks, staged edge counts)
+struct EstEdges {
+    const uint32_t *q;
+    const uint32_t *wedges;
+    const uint64_t *optr;
+    __device__ uint32_t rank(size_t i) const { return q[i]; }
+    __device__ uint64_t outdeg(size_t i) const { return optr[q[i] + 1] - optr[q[i]]; }
+    __device__ uint32_t est(size_t i) const { return root_est(wedges[q[i]], outdeg(i)); }
+};
+
+// Learned queue keys: tier (2 bits) | 24-bit priority of the predicted log-work
+// (kc_learned_prio) | rank; the estimate is the predicted work, in 1/64 units.
+struct EstLearned {
+    const uint64_t *keys;
+    const uint64_t *optr;
+    __device__ uint32_t rank(size_t i) const { return (uint32_t)keys[i]; }
+    __device__ uint64_t outdeg(size_t i) const { return optr[rank(i) + 1] - optr[rank(i)]; }
+    __device__ uint32_t est(size_t i) const {
+        const uint32_t prio = (uint32_t)(keys[i] >> 32) & 0xFFFFFFu;
+        const double e = 64.0 * expm1(kc_learned_logwork(prio));
+        return e >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)e;
+    }
+};
+
+template <class Est>
+__global__ void k_est_sum(Est E, uint32_t cnt, WqAux *a) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint64_t c = i < cnt ? est_of(q, i, wedges, optr) : 0u;
+    uint64_t c = i < cnt ? E.est(i) : 0u;
     for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
     if ((threadIdx.x & 63u) == 0 && c) atomicAdd(&a->sum, (double)c);
 }
 
-// 8-bit bucket of an edge count, more edges first: 255 - (8 * floor(log2 c) + the
-// next three bits of c).
-__device__ __forceinline__ uint32_t edge_bucket(uint32_t c) {
+// 8-bit bucket of an estimate, larger first: 255 - (8 * floor(log2 c) + the next
+// three bits of c).
+__device__ __forceinline__ uint32_t est_bucket(uint32_t c) {
     if (c == 0) return 255u;
     const uint32_t e = 31u - (uint32_t)__builtin_clz(c);
     const uint32_t m = e >= 3 ? (c >> (e - 3)) & 7u : (c << (3 - e)) & 7u;
@@ -196,28 +161,27 @@ __device__ __forceinline__ uint32_t edge_bucket(uint32_t c) {
     return 255u - (key > 255u ? 255u : key);
 }
 
-__global__ void k_root_parts(const uint32_t *q, const uint32_t *wedges, uint32_t cnt, const uint64_t *optr, WqAux *a,
-                             uint32_t *parts) {
+template <class Est>
+__global__ void k_root_parts(Est E, uint32_t cnt, WqAux *a, uint32_t *parts) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cnt) return;
     const double tot = a->sum;
     double target = 4.0 * tot / (double)cnt;
     if (tot / 1024.0 < target) target = tot / 1024.0;
     if (target < 1.0) target = 1.0;
-    const uint32_t u = q[i];
-    const uint64_t d = optr[u + 1] - optr[u];
-    const uint32_t c = root_est(wedges[u], d);
+    const uint64_t d = E.outdeg(i);
+    const uint32_t c = E.est(i);
     double np = ceil((double)c / target);
     const double cap = d < 64 ? (double)(d ? d : 1) : 64.0;
     np = np < 1.0 ? 1.0 : (np > cap ? cap : np);
     parts[i] = (uint32_t)np;
-    atomicAdd(&a->bcnt[edge_bucket(c)], (uint32_t)np);
+    atomicAdd(&a->bcnt[est_bucket(c)], (uint32_t)np);
 }
 
 constexpr uint32_t WQ_SKIP = 0xFFFFFFFFu;
 
-__global__ void k_emit_items(const uint32_t *q, const uint32_t *wedges, const uint64_t *optr, const uint32_t *parts,
-                             uint32_t cnt, WqAux *a, uint32_t bound, uint64_t *items) {
+template <class Est>
+__global__ void k_emit_items(Est E, const uint32_t *parts, uint32_t cnt, WqAux *a, uint32_t bound, uint64_t *items) {
     __shared__ uint32_t base[256];
     __shared__ uint32_t s_total;
     const uint32_t tid = threadIdx.x;
@@ -236,7 +200,7 @@ __global__ void k_emit_items(const uint32_t *q, const uint32_t *wedges, const ui
     __syncthreads();
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + tid; i < cnt; i += stride) {
-        const uint32_t u = q[i], b = edge_bucket(est_of(q, i, wedges, optr)), np = parts[i];
+        const uint32_t u = E.rank(i), b = est_bucket(E.est(i)), np = parts[i];
         const uint32_t off = base[b] + atomicAdd(&a->bcur[b], np);
         for (uint32_t pt = 0; pt < np; ++pt)
             if (off + pt < bound) items[off + pt] = ((uint64_t)u << 32) | ((uint64_t)pt << 16) | (uint64_t)np;
@@ -251,27 +215,34 @@ inline uint32_t work_items_bound(uint32_t cnt) {
     return cnt + extra + 1;
 }
 
+// Items of cnt roots into a new device list (owned by the caller, bound entries).
+template <class Est>
+kc_status build_items(const Est &E, uint32_t cnt, hipStream_t s, uint64_t **items, uint32_t *bound_out) {
+    const uint32_t bound = work_items_bound(cnt);
+    kc_tmp aux, parts;
+    KC_TRY(kc_tmp_alloc(aux, sizeof(WqAux), s));
+    KC_TRY(kc_tmp_alloc(parts, (size_t)cnt * 4, s));
+    KC_TRY(kc_dev_alloc((void **)items, (size_t)bound * 8, s));
+    WqAux *a = aux.as<WqAux>();
+    hipLaunchKernelGGL(k_wq_clear, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_est_sum<Est>, dim3(grid_for(cnt)), dim3(T), 0, s, E, cnt, a);
+    hipLaunchKernelGGL(k_root_parts<Est>, dim3(grid_for(cnt)), dim3(T), 0, s, E, cnt, a, parts.as<uint32_t>());
+    hipLaunchKernelGGL(k_emit_items<Est>, dim3(grid_for(bound)), dim3(T), 0, s, E,
+                       (const uint32_t *)parts.as<uint32_t>(), cnt, a, bound, *items);
+    KC_HIP(hipGetLastError());
+    *bound_out = bound;
+    return KC_OK;
+}
+
 kc_status build_work_items(kc_graph *g, uint32_t first, uint32_t cnt) {
     hipStream_t s = g->stream;
     kc_cache_free(g->wq, s);
     g->wq = nullptr;
     g->wq_count = 0;
     g->wq_ready = 0;
-    const uint32_t bound = work_items_bound(cnt);
-    const uint32_t *q = g->dq + first;
-    kc_tmp aux, parts;
-    KC_TRY(kc_tmp_alloc(aux, sizeof(WqAux), s));
-    KC_TRY(kc_tmp_alloc(parts, (size_t)cnt * 4, s));
-    KC_TRY(kc_dev_alloc((void **)&g->wq, (size_t)bound * 8, s));
-    WqAux *a = aux.as<WqAux>();
-    hipLaunchKernelGGL(k_wq_clear, dim3(1), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_edge_sum, dim3(grid_for(cnt)), dim3(T), 0, s, q, cnt, (const uint32_t *)g->wedges,
-                       (const uint64_t *)g->optr, a);
-    hipLaunchKernelGGL(k_root_parts, dim3(grid_for(cnt)), dim3(T), 0, s, q, (const uint32_t *)g->wedges, cnt,
-                       (const uint64_t *)g->optr, a, parts.as<uint32_t>());
-    hipLaunchKernelGGL(k_emit_items, dim3(grid_for(bound)), dim3(T), 0, s, q, (const uint32_t *)g->wedges,
-                       (const uint64_t *)g->optr, (const uint32_t *)parts.as<uint32_t>(), cnt, a, bound, g->wq);
-    KC_HIP(hipGetLastError());
+    EstEdges E{g->dq + first, g->wedges, g->optr};
+    uint32_t bound = 0;
+    KC_TRY(build_items(E, cnt, s, &g->wq, &bound));
     g->wq_count = bound;
     g->wq_first = first;
     g->wq_roots = cnt;
@@ -339,10 +310,82 @@ kc_status build_degree_cache(kc_graph *g, uint32_t wd) {
 
 }  // namespace
 
-kc_status kc_predict_work(const kc_graph *g, int k, float *d_pred, hipStream_t s);
+// Smallest out-degree d in [lo, hi] whose unpruned work bound, the number of l-cliques
+// of a complete G+(u) for l = 1..k-2, reaches e^promote; hi + 1 if none does.
+static uint32_t promote_outdeg(int k, float promote, uint32_t lo, uint32_t hi) {
+    for (uint32_t d = lo; d <= hi; ++d) {
+        double c = 1.0, w = 0.0;
+        for (int l = 1; l <= k - 2; ++l) {
+            c = c * (double)(d - l + 1) / (double)l;
+            w += c;
+        }
+        if (w > 0.0 && log(w) >= (double)promote) return d;
+    }
+    return hi + 1;
+}
+
+// Learned queue of clique size k (cached on the handle): candidates are the roots
+// above the one-wave limit and the one-wave roots whose work bound reaches the
+// promotion threshold, a prefix of the degree queue (sorted by out-degree).
+static kc_status build_learned(kc_graph *g, int k, uint32_t wd, uint32_t dcap, kc_graph::LearnedQueue &L) {
+    hipStream_t s = g->stream;
+    const uint64_t *hist = g->dq_hist;
+    const uint32_t dmax = g->max_outdeg;
+    const char *pe = getenv("KC_PROMOTE_LOGWORK");
+    const float promote = pe ? (float)atof(pe) : 14.0f;  // predicted work above ~1.2e6 intersections
+    const uint32_t lo = (uint32_t)(k - 1) > 2u ? (uint32_t)(k - 1) : 2u;
+    const uint32_t dmin = promote_outdeg(k, promote, lo, wd);
+    uint32_t active = g->dq_wide, cand = g->dq_wide;
+    for (uint32_t d = lo; d <= wd && d <= dmax; ++d) {
+        active += (uint32_t)hist[d];
+        if (d >= dmin) cand += (uint32_t)hist[d];
+    }
+    kc_cache_free(L.queue, s);
+    kc_cache_free(L.items, s);
+    L = kc_graph::LearnedQueue();
+    KC_TRY(kc_dev_alloc((void **)&L.queue, (size_t)(active ? active : 1) * 4, s));
+    uint32_t h_stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    kc_tmp keys, tmp, stats;
+    if (cand) {
+        KC_TRY(kc_tmp_alloc(keys, (size_t)cand * 8, s));
+        KC_TRY(kc_tmp_alloc(tmp, (size_t)cand * 8, s));
+        KC_TRY(kc_tmp_alloc(stats, 8 * 4, s));
+        KC_HIP(hipMemsetAsync(stats.p, 0, 8 * 4, s));
+        KC_TRY(kc_learned_keys(g, k, cand, wd, dcap, promote, keys.as<uint64_t>(), stats.as<uint32_t>(), s));
+        KC_TRY(kc_radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), cand, 32, 64, s));
+        hipLaunchKernelGGL(k_queue_from_keys, dim3(grid_for(cand)), dim3(T), 0, s, (const uint64_t *)keys.as<uint64_t>(),
+                           cand, L.queue);
+        KC_HIP(hipGetLastError());
+        uint32_t *h = (uint32_t *)kc_pinned_scratch();
+        KC_HIP(hipMemcpyAsync(h, stats.p, 8 * 4, hipMemcpyDeviceToHost, s));
+        KC_TRY(kc_sync(s));
+        for (int i = 0; i < 8; ++i) h_stats[i] = h[i];
+    }
+    // the one-wave roots below the promotion bound keep their degree order after the candidates
+    if (active > cand)
+        KC_HIP(hipMemcpyAsync(L.queue + cand, g->dq + cand, (size_t)(active - cand) * 4, hipMemcpyDeviceToDevice, s));
+    // kc_queue order: [0] one-wave, [1] workgroup, [2] scratch (the buffer holds them in reverse)
+    L.count[2] = h_stats[0];
+    L.count[1] = h_stats[1];
+    L.count[0] = h_stats[2] + (active - cand);
+    L.max_d[2] = h_stats[4];
+    L.max_d[1] = h_stats[5];
+    uint32_t wmax = h_stats[6];
+    for (uint32_t d = lo; d < dmin && d <= wd && d <= dmax; ++d)
+        if (hist[d]) wmax = d > wmax ? d : wmax;
+    L.max_d[0] = wmax;
+    if (k >= 5 && L.count[1]) {
+        EstLearned E{keys.as<uint64_t>() + L.count[2], g->optr};
+        KC_TRY(build_items(E, L.count[1], s, &L.items, &L.item_count));
+    }
+    L.wd = (int)wd;
+    L.dcap = dcap;
+    L.wserial = g->mlp_serial;
+    L.ready = 1;
+    return KC_OK;
+}
 
 kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_max, kc_queue &q, bool no_alloc) {
-    hipStream_t s = g->stream;
     const uint32_t n = g->n;
     for (int t = 0; t < 3; ++t) {
         q.ptr[t] = nullptr;
@@ -352,14 +395,32 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
     int wd = kc_tuning_now().wave_dmax;
     wd = wd < 1 ? 1 : (wd > 64 ? 64 : wd);
     if ((uint32_t)wd > d_lds_max) wd = (int)d_lds_max;
-
-    if (no_alloc) policy = KC_SCHED_DEGREE;
-    if (policy == KC_SCHED_DEGREE) {
-        kc_graph *gm = const_cast<kc_graph *>(g);
-        if (!g->dq_ready || g->dq_wd != wd) {
-            if (no_alloc) return kc_fail(KC_ESTATE, "the handle's degree queue is not built (count once with kc_count)");
-            KC_TRY(build_degree_cache(gm, (uint32_t)wd));
+    kc_graph *gm = const_cast<kc_graph *>(g);
+    if (no_alloc) policy = KC_SCHED_EDGES;
+    if (policy == KC_SCHED_LEARNED && !g->mlp_loaded)
+        return kc_fail(KC_ESTATE, "learned schedule requested but no MLP weights are loaded");
+    if (!g->dq_ready || g->dq_wd != wd) {
+        if (no_alloc) return kc_fail(KC_ESTATE, "the handle's degree queue is not built (count once with kc_count)");
+        KC_TRY(build_degree_cache(gm, (uint32_t)wd));
+    }
+    if (policy == KC_SCHED_LEARNED && k >= 5) {
+        kc_graph::LearnedQueue &L = gm->lq[k];
+        if (!L.ready || L.wd != wd || L.dcap != d_lds_max || L.wserial != g->mlp_serial)
+            KC_TRY(build_learned(gm, k, (uint32_t)wd, d_lds_max, L));
+        q.ptr[2] = L.queue;
+        q.ptr[1] = L.queue + L.count[2];
+        q.ptr[0] = L.queue + L.count[2] + L.count[1];
+        for (int t = 0; t < 3; ++t) {
+            q.count[t] = L.count[t];
+            q.max_d[t] = L.max_d[t];
         }
+        q.wg_items = L.items;
+        q.wg_item_count = L.items ? L.item_count : 0;
+        q.wg_ncls = 0;
+        return KC_OK;
+    }
+    {
+        hipStream_t s = g->stream;
         const uint64_t *hist = g->dq_hist;
         const uint32_t dmax = g->max_outdeg;
         uint32_t scratch = 0, narrow = 0;
@@ -401,6 +462,7 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
             off += (uint32_t)hist[d];
         }
         if (off != q.count[1]) q.wg_ncls = 0;  // not a plain degree order: one launch
+        if (policy == KC_SCHED_DEGREE) return KC_OK;  // whole roots in out-degree order
         // From k = 5 on, the heaviest roots of the tier take most of its time, one
         // workgroup each: roots above twice the one-wave bound are split over
         // several items (Section 7, the (u, v) split), one per 32 first-level
@@ -446,77 +508,4 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
         }
         return KC_OK;
     }
-
-    if (!g->mlp_loaded) return kc_fail(KC_ESTATE, "learned schedule requested but no MLP weights are loaded");
-    kc_tmp keys, keys2, tmp, flag, pos, stats, pred;
-    KC_TRY(kc_tmp_alloc(keys, (size_t)n * 8, s));
-    KC_TRY(kc_tmp_alloc(flag, (size_t)n * 4, s));
-    KC_TRY(kc_tmp_alloc(pos, (size_t)n * 4, s));
-    KC_TRY(kc_tmp_alloc(stats, 8 * 4, s));
-    KC_TRY(kc_tmp_alloc(pred, (size_t)n * 4, s));
-    KC_HIP(hipMemsetAsync(stats.p, 0, 8 * 4, s));
-    KC_TRY(kc_predict_work(g, k, pred.as<float>(), s));
-    const char *pe = getenv("KC_PROMOTE_LOGWORK");
-    const float promote = pe ? (float)atof(pe) : 14.0f;  // predicted work above ~1.2e6 intersections
-    hipLaunchKernelGGL(k_learned_keys, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)g->optr, n, k, (uint32_t)wd,
-                       d_lds_max,
-                       (const float *)pred.as<float>(), promote, keys.as<uint64_t>(), flag.as<uint32_t>(),
-                       stats.as<uint32_t>(), stats.as<uint32_t>() + 4);
-    KC_HIP(hipGetLastError());
-    KC_TRY(kc_scan_excl_u32(flag.as<uint32_t>(), pos.as<uint32_t>(), n, nullptr, s));
-    uint32_t *h_stats = (uint32_t *)kc_pinned_scratch();
-    KC_HIP(hipMemcpyAsync(h_stats, stats.p, 8 * 4, hipMemcpyDeviceToHost, s));
-    KC_TRY(kc_sync(s));
-    const uint32_t total = h_stats[0] + h_stats[1] + h_stats[2];
-    uint32_t off = 0;
-    for (int t = 0; t < 3; ++t) {
-        q.count[t] = h_stats[t];
-        q.max_d[t] = h_stats[4 + t];
-    }
-    if (total == 0) return KC_OK;
-    KC_TRY(kc_tmp_alloc(keys2, (size_t)total * 8, s));
-    KC_TRY(kc_tmp_alloc(tmp, (size_t)total * 8, s));
-    hipLaunchKernelGGL(k_compact_keys, dim3(grid_for(n)), dim3(T), 0, s, (const uint64_t *)keys.as<uint64_t>(),
-                       (const uint32_t *)flag.as<uint32_t>(), (const uint32_t *)pos.as<uint32_t>(), n,
-                       keys2.as<uint64_t>());
-    KC_HIP(hipGetLastError());
-    KC_TRY(kc_radix_sort_u64(keys2.as<uint64_t>(), tmp.as<uint64_t>(), total, 32, 64, s));
-    KC_TRY(kc_tmp_alloc(q.buf, (size_t)total * 4, s));
-    hipLaunchKernelGGL(k_queue_from_keys, dim3(grid_for(total)), dim3(T), 0, s,
-                       (const uint64_t *)keys2.as<uint64_t>(), total, q.buf.as<uint32_t>());
-    KC_HIP(hipGetLastError());
-    for (int t = 0; t < 3; ++t) {
-        q.ptr[t] = q.buf.as<uint32_t>() + off;
-        off += q.count[t];
-    }
-    // heavy workgroup-tier roots are split over several items (k >= 5)
-    if (k >= 5 && q.count[1]) {
-        const uint32_t c1 = q.count[1];
-        kc_tmp sum, parts, offs, ntot;
-        KC_TRY(kc_tmp_alloc(sum, 8, s));
-        KC_TRY(kc_tmp_alloc(parts, (size_t)c1 * 4, s));
-        KC_TRY(kc_tmp_alloc(offs, (size_t)c1 * 4, s));
-        KC_TRY(kc_tmp_alloc(ntot, 4, s));
-        KC_HIP(hipMemsetAsync(sum.p, 0, 8, s));
-        hipLaunchKernelGGL(k_work_sum, dim3(grid_for(c1)), dim3(T), 0, s, q.ptr[1], c1,
-                           (const float *)pred.as<float>(), sum.as<double>());
-        const char *sp = getenv("KC_SPLIT_ITEMS");  // items the tier's predicted work is cut into
-        const double per = sp ? atof(sp) : 4096.0;
-        hipLaunchKernelGGL(k_split_parts, dim3(grid_for(c1)), dim3(T), 0, s, q.ptr[1], c1,
-                           (const float *)pred.as<float>(), (const double *)sum.as<double>(), per, 64u,
-                           parts.as<uint32_t>());
-        KC_TRY(kc_scan_excl_u32(parts.as<uint32_t>(), offs.as<uint32_t>(), c1, ntot.as<uint32_t>(), s));
-        uint32_t *hn = (uint32_t *)kc_pinned_scratch();
-        KC_HIP(hipMemcpyAsync(hn, ntot.p, 4, hipMemcpyDeviceToHost, s));
-        KC_TRY(kc_sync(s));
-        const uint32_t nitems = hn[0];
-        KC_TRY(kc_tmp_alloc(q.items_buf, (size_t)nitems * 8, s));
-        hipLaunchKernelGGL(k_split_emit, dim3(grid_for(c1)), dim3(T), 0, s, q.ptr[1], c1,
-                           (const uint32_t *)parts.as<uint32_t>(), (const uint32_t *)offs.as<uint32_t>(),
-                           q.items_buf.as<uint64_t>());
-        KC_HIP(hipGetLastError());
-        q.wg_items = q.items_buf.as<uint64_t>();
-        q.wg_item_count = nitems;
-    }
-    return KC_OK;
 }

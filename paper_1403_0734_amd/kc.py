@@ -15,8 +15,9 @@ LIB_PATH = os.path.join(PKG, "libkc.so")
 
 KC_OK, KC_EINVAL, KC_ESTATE, KC_ENOMEM, KC_EOVERFLOW, KC_EDEVICE = 0, -1, -2, -3, -4, -5
 KC_COLOR_PER_ROOT, KC_COLOR_GLOBAL = 0, 1
-KC_SCHED_DEGREE, KC_SCHED_LEARNED = 0, 1
+KC_SCHED_DEGREE, KC_SCHED_LEARNED, KC_SCHED_EDGES = 0, 1, 2
 KC_KMAX = 10
+KC_MLP_PARAMS = 1377
 
 # every symbol include/kc.h declares
 EXPORTS = [
@@ -24,6 +25,7 @@ EXPORTS = [
     "kc_count_batch", "kc_set_schedule", "kc_train_schedule", "kc_graph_info", "kc_get_csr",
     "kc_get_oriented", "kc_last_timings", "kc_graph_destroy", "kc_status_str",
     "kc_set_tuning", "kc_get_tuning", "kc_autotune", "kc_last_tier_timings", "kc_count_noalloc",
+    "kc_predict_work", "kc_mlp_step",
 ]
 
 
@@ -41,7 +43,7 @@ class kc_estimate(ctypes.Structure):
 class kc_tuning(ctypes.Structure):
     _fields_ = [("wave_dmax", ctypes.c_int32), ("wg_blocks_per_cu", ctypes.c_int32),
                 ("wave_blocks_per_cu", ctypes.c_int32), ("queue_chunk_div", ctypes.c_int32),
-                ("wg_dmax", ctypes.c_int32), ("local_bits", ctypes.c_int32)]
+                ("wg_dmax", ctypes.c_int32), ("local_bits", ctypes.c_int32), ("wg_waves", ctypes.c_int32)]
 
 
 _lib = None
@@ -64,6 +66,8 @@ def load(path: str = LIB_PATH):
         "kc_count_pair_sampled": (i32, [P, i32, ctypes.c_double, u64, ctypes.POINTER(kc_estimate)]),
         "kc_count_per_root": (i32, [P, i32, P, P]),
         "kc_count_noalloc": (i32, [P, i32, P]),
+        "kc_predict_work": (i32, [P, i32, P, P]),
+        "kc_mlp_step": (i32, [P, P, P, i32, ctypes.c_float, P, P, u32, P, ctypes.POINTER(ctypes.c_float), P]),
         "kc_count_batch": (i32, [P, u32, i32, P]),
         "kc_set_schedule": (i32, [P, i32, ctypes.c_char_p]),
         "kc_train_schedule": (i32, [P, u32, i32, i32, u64, ctypes.c_char_p, ctypes.POINTER(ctypes.c_float)]),
@@ -166,11 +170,11 @@ def kc_train_schedule(gs, k: int, epochs: int, seed: int, weights_path: str) -> 
 
 
 def kc_set_tuning(wave_dmax=64, wg_blocks_per_cu=0, wave_blocks_per_cu=8, queue_chunk_div=8, wg_dmax=0,
-                  local_bits=128, defaults=False):
+                  local_bits=128, wg_waves=0, defaults=False):
     if defaults:
         check(load().kc_set_tuning(None), "kc_set_tuning")
         return
-    t = kc_tuning(wave_dmax, wg_blocks_per_cu, wave_blocks_per_cu, queue_chunk_div, wg_dmax, local_bits)
+    t = kc_tuning(wave_dmax, wg_blocks_per_cu, wave_blocks_per_cu, queue_chunk_div, wg_dmax, local_bits, wg_waves)
     check(load().kc_set_tuning(ctypes.byref(t)), "kc_set_tuning")
 
 
@@ -186,6 +190,21 @@ def kc_autotune(gs, k: int, cache_path: str | None = None) -> dict:
     check(load().kc_autotune(arr, len(gs), k, cache_path.encode() if cache_path else None, ctypes.byref(t)),
           "kc_autotune")
     return {f: getattr(t, f) for f, _ in kc_tuning._fields_}
+
+
+def kc_predict_work(g: int, k: int, dev_pred, dev_feat=None):
+    """The scheduler MLP's predicted log(1 + work) per root (device float[n], by
+    original id) and optionally its raw features (device float[n][8])."""
+    check(load().kc_predict_work(g, k, _ptr(dev_pred), _ptr(dev_feat)), f"kc_predict_work(k={k})")
+
+
+def kc_mlp_step(params, adam_m, adam_v, step: int, lr: float, x, t, count: int, grad=None, stream=None) -> float:
+    """One gradient + Adam step of the scheduler MLP on device samples; returns the
+    batch loss before the update."""
+    loss = ctypes.c_float()
+    check(load().kc_mlp_step(_ptr(params), _ptr(adam_m), _ptr(adam_v), step, float(lr), _ptr(x), _ptr(t), count,
+                             _ptr(grad), ctypes.byref(loss), stream), "kc_mlp_step")
+    return loss.value
 
 
 def kc_graph_info(g: int):

@@ -51,13 +51,16 @@ def test_learned_schedule_counts_equal(stream, tmp_path):
     el = S.planted_small(5000, 0.003, [list(range(i, i + 28)) for i in range(0, 4000, 400)], 3)
     og = O.OracleGraph.from_edgelist(el)
     h = graph_on(el, stream)
-    for k in range(3, 8):
-        announce(f"learned vs degree k={k}")
+    for k in range(3, 9):
+        announce(f"learned vs degree vs edges k={k}")
         K.kc_set_schedule(h, K.KC_SCHED_DEGREE)
         qd = K.kc_count(h, k)
+        K.kc_set_schedule(h, K.KC_SCHED_EDGES)
+        qe = K.kc_count(h, k)
         K.kc_set_schedule(h, K.KC_SCHED_LEARNED, wpath)
         ql = K.kc_count(h, k)
-        assert qd == ql == og.count(k), k
+        assert qd == qe == ql == og.count(k), k
+        assert K.kc_count(h, k) == ql  # the learned queue of this k, cached
         c, _ = per_root(h, el.n, k)
         assert np.array_equal(c, og.count_per_root(k))
     # colour sampling under the learned schedule
@@ -82,6 +85,151 @@ def test_learned_schedule_on_held_out_graph(stream, tmp_path):
     assert np.array_equal(work, inter)
     for g in train + [h]:
         K.kc_graph_destroy(g)
+
+
+# ---------------------------------------------------------------------------
+# The MLP's fp32 kernels against torch (fp32 forward, autograd gradient, Adam)
+
+def _mlp_layout(P):
+    P = np.asarray(P)
+    return (P[0:256].reshape(32, 8), P[256:288], P[288:1312].reshape(32, 32), P[1312:1344], P[1344:1376], P[1376])
+
+
+def _torch_forward(P, x):
+    import torch
+    W1, b1, W2, b2, w3, b3 = _mlp_layout(P)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32)
+    h1 = torch.relu(t(x) @ t(W1).T + t(b1))
+    h2 = torch.relu(h1 @ t(W2).T + t(b2))
+    return (h2 @ t(w3) + float(b3)).numpy()
+
+
+def _write_weights(path, params, norm):
+    with open(path, "wb") as f:
+        f.write(b"KCMLP001")
+        f.write(np.uint32(K.KC_MLP_PARAMS).tobytes())
+        f.write(np.asarray(norm, np.float32).tobytes())
+        f.write(np.asarray(params, np.float32).tobytes())
+
+
+def _features_from_oracle(og, k):
+    """The eight scheduler features recomputed in float64 from the oracle's Gamma+
+    lists and per-root triangle counts (edges of G+(u)), by original id."""
+    import math
+    hp, hn = og.high_csr()
+    dplus = np.diff(hp.astype(np.int64))
+    deg = og.degrees().astype(np.float64)
+    ep = og.count_per_root(3).astype(np.float64)
+    n = og.n
+    wed = np.zeros(n)
+    mx = np.zeros(n)
+    for u in range(n):
+        nb = hn[hp[u]:hp[u + 1]]
+        if len(nb):
+            wed[u] = dplus[nb].sum()
+            mx[u] = dplus[nb].max()
+    pairs = np.where(dplus >= 2, 0.5 * dplus * (dplus - 1), 0.0)
+    dens = np.divide(ep, pairs, out=np.zeros(n), where=pairs > 0)
+    lc = np.full(n, -10.0)
+    r = k - 1
+    for u in range(n):
+        if dplus[u] >= r and dens[u] > 0:
+            v = (math.lgamma(dplus[u] + 1) - math.lgamma(r + 1) - math.lgamma(dplus[u] - r + 1)
+                 + 0.5 * r * (r - 1) * math.log(dens[u]))
+            lc[u] = min(max(v, -10.0), 60.0)
+    f = np.stack([np.log1p(dplus), np.log1p(wed), np.log1p(mx), np.log1p(deg), np.log1p(ep), dens,
+                  np.full(n, k / 10.0), lc], 1)
+    return f.astype(np.float32), dplus
+
+
+def test_mlp_forward_matches_torch(stream, tmp_path):
+    """kc_predict_work (features + the fp32 inference kernel) against the oracle's
+    features and a torch fp32 forward pass of the same weight file."""
+    import torch
+    rng = np.random.default_rng(5)
+    params = (rng.standard_normal(K.KC_MLP_PARAMS) * 0.3).astype(np.float32)
+    norm = np.array([2, 5, 4, 3, 4, 0.3, 0.5, 0, 1, 2, 2, 1, 2, 0.3, 0.2, 5, 3, 2], np.float32)
+    wpath = str(tmp_path / "w.bin")
+    _write_weights(wpath, params, norm)
+    el = S.planted_small(3000, 0.004, [list(range(i, i + 25)) for i in range(0, 2500, 500)], 9)
+    og = O.OracleGraph.from_edgelist(el)
+    h = graph_on(el, stream)
+    K.kc_set_schedule(h, K.KC_SCHED_LEARNED, wpath)
+    for k in (4, 7):
+        announce(f"MLP forward k={k}")
+        pred = torch.zeros(el.n, dtype=torch.float32, device="cuda:0")
+        feat = torch.zeros(el.n * 8, dtype=torch.float32, device="cuda:0")
+        K.kc_predict_work(h, k, pred.data_ptr(), feat.data_ptr())
+        torch.cuda.synchronize()
+        f = feat.cpu().numpy().reshape(el.n, 8)
+        want_f, dplus = _features_from_oracle(og, k)
+        np.testing.assert_allclose(f, want_f, rtol=2e-6, atol=1e-6)
+        x = (f - norm[:8]) / norm[8:16]
+        y = _torch_forward(params, x) * norm[17] + norm[16]
+        active = dplus >= k - 1
+        p = pred.cpu().numpy()
+        np.testing.assert_allclose(p[active], y[active], rtol=1e-5, atol=1e-5)
+        assert np.all(p[~active] == 0)
+    K.kc_graph_destroy(h)
+
+
+def test_mlp_step_matches_torch_autograd(stream):
+    """kc_mlp_step (the gradient and Adam kernels of the training loop) against torch
+    autograd of 0.5 * mean (y - t)^2 and the Adam update, over three steps with
+    batches of 200, 137 and 64 samples (ragged 64-sample blocks)."""
+    import torch
+    rng = np.random.default_rng(17)
+    P = (rng.standard_normal(K.KC_MLP_PARAMS) * 0.3).astype(np.float32)
+    dev = torch.device("cuda:0")
+    dP = torch.from_numpy(P.copy()).to(dev)
+    dM = torch.zeros_like(dP)
+    dV = torch.zeros_like(dP)
+    dG = torch.zeros_like(dP)
+    m = np.zeros(K.KC_MLP_PARAMS)
+    v = np.zeros(K.KC_MLP_PARAMS)
+    lr = 2e-3
+    for step, count in enumerate([200, 137, 64], start=1):
+        x = rng.standard_normal((count, 8)).astype(np.float32)
+        t = rng.standard_normal(count).astype(np.float32)
+        dx = torch.from_numpy(x).to(dev)
+        dt = torch.from_numpy(t).to(dev)
+        torch.cuda.synchronize()
+        p_before = dP.cpu().numpy().astype(np.float32)
+        loss = K.kc_mlp_step(dP.data_ptr(), dM.data_ptr(), dV.data_ptr(), step, lr, dx.data_ptr(), dt.data_ptr(),
+                             count, dG.data_ptr(), bs_stream(stream))
+        torch.cuda.synchronize()
+        # torch autograd at the parameters before the step
+        tp = torch.tensor(p_before, dtype=torch.float32, requires_grad=True)
+        W1 = tp[0:256].reshape(32, 8)
+        b1 = tp[256:288]
+        W2 = tp[288:1312].reshape(32, 32)
+        b2 = tp[1312:1344]
+        w3 = tp[1344:1376]
+        b3 = tp[1376]
+        y = torch.relu(torch.relu(torch.from_numpy(x) @ W1.T + b1) @ W2.T + b2) @ w3 + b3
+        tl = 0.5 * ((y - torch.from_numpy(t)) ** 2).mean()
+        tl.backward()
+        g_ref = tp.grad.numpy()
+        g = dG.cpu().numpy()
+        np.testing.assert_allclose(g, g_ref, rtol=1e-4, atol=2e-6)
+        assert loss == pytest.approx(float(tl), rel=1e-5)
+        # Adam from the library's gradient, in float64 with the kernel's fp32 constants
+        # (1 - beta2 rounds to 0.00099998713 in fp32)
+        f32 = np.float32
+        b1, b2 = float(f32(0.9)), float(f32(0.999))
+        ob1, ob2 = float(f32(1) - f32(0.9)), float(f32(1) - f32(0.999))
+        c1, c2 = float(f32(1) - f32(0.9) ** step), float(f32(1) - f32(0.999) ** step)
+        gd = g.astype(np.float64)
+        m = b1 * m + ob1 * gd
+        v = b2 * v + ob2 * gd * gd
+        want = p_before - float(f32(lr)) * (m / c1) / (np.sqrt(v / c2) + 1e-8)
+        np.testing.assert_allclose(dP.cpu().numpy(), want, rtol=1e-5, atol=1e-6)
+        np.testing.assert_allclose(dM.cpu().numpy(), m, rtol=1e-5, atol=1e-9)
+        np.testing.assert_allclose(dV.cpu().numpy(), v, rtol=1e-5, atol=1e-12)
+
+
+def bs_stream(stream):
+    return stream.cuda_stream
 
 
 def test_bad_weight_file(stream, tmp_path):
@@ -140,11 +288,12 @@ def test_batch_default_stream_and_destroy():
         K.kc_graph_destroy(h)
 
 
-TUNING_FIELDS = ["wave_dmax", "wg_blocks_per_cu", "wave_blocks_per_cu", "queue_chunk_div", "wg_dmax", "local_bits"]
+TUNING_FIELDS = ["wave_dmax", "wg_blocks_per_cu", "wave_blocks_per_cu", "queue_chunk_div", "wg_dmax", "local_bits",
+                 "wg_waves"]
 
 
-@pytest.mark.parametrize("tuning", [(16, 0, 8, 8, 0, 128), (24, 2, 4, 4, 0, 64), (48, 1, 16, 64, 64, 128),
-                                    (64, 8, 1, 1, 0, 128), (1, 0, 8, 8, 100, 64)])
+@pytest.mark.parametrize("tuning", [(16, 0, 8, 8, 0, 128, 0), (24, 2, 4, 4, 0, 64, 8), (48, 1, 16, 64, 64, 128, 16),
+                                    (64, 8, 1, 1, 0, 128, 4), (1, 0, 8, 8, 100, 64, 16)])
 def test_tunables_never_change_counts(stream, tuning):
     els = batch_graphs()
     want5 = [O.OracleGraph.from_edgelist(el).count(5) for el in els]
@@ -162,12 +311,12 @@ def test_tunables_never_change_counts(stream, tuning):
 
 def test_tuning_rejects_bad_values():
     for bad in [(0, 0, 8, 8), (65, 0, 8, 8), (64, 9, 8, 8), (64, 0, 0, 8), (64, 0, 8, 65), (64, 0, 8, 8, 63),
-                (64, 0, 8, 8, 65536), (64, 0, 8, 8, 0, 96)]:
+                (64, 0, 8, 8, 65536), (64, 0, 8, 8, 0, 96), (64, 0, 8, 8, 0, 128, 12)]:
         with pytest.raises(K.KcError) as e:
             K.kc_set_tuning(*bad)
         assert e.value.status == K.KC_EINVAL
     K.kc_set_tuning(defaults=True)
-    assert K.kc_get_tuning() == dict(zip(TUNING_FIELDS, (64, 0, 8, 8, 0, 128)))
+    assert K.kc_get_tuning() == dict(zip(TUNING_FIELDS, (64, 0, 8, 8, 0, 128, 0)))
 
 
 def test_autotune_cache(stream, tmp_path):
