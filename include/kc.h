@@ -245,6 +245,10 @@ kc_status kc_get_oriented(const kc_graph *g, uint64_t *optr, uint32_t *ocol, uin
  * tier kernel alone (one-wave, workgroup, scratch; 0 for an empty tier). */
 kc_status kc_last_timings(const kc_graph *g, float *ms_schedule, float *ms_count, float *ms_total);
 kc_status kc_last_tier_timings(const kc_graph *g, float *ms_wave, float *ms_workgroup, float *ms_scratch);
+/* The tier kernels of the staging pass (G+(u) into the handle's cache) of the last
+ * count that staged: one-wave, workgroup and scratch kernels (milliseconds, HIP
+ * events on the bound stream; 0 for an empty tier). */
+kc_status kc_last_stage_timings(const kc_graph *g, float *ms_wave, float *ms_workgroup, float *ms_scratch);
 
 void kc_graph_destroy(kc_graph *g);
 const char *kc_status_str(kc_status s);

@@ -112,6 +112,8 @@ void kc_graph_destroy(kc_graph *g) {
     delete[] g->dq_hist;
     for (hipEvent_t e : g->ev)
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : g->sev)
+        if (e) (void)hipEventDestroy(e);
     if (g->fork) (void)hipEventDestroy(g->fork);
     if (g->join) (void)hipEventDestroy(g->join);
     if (g->side) (void)hipStreamDestroy(g->side);
@@ -127,6 +129,7 @@ static kc_status create_impl(const uint32_t *src, const uint32_t *dst, uint64_t 
     g->idbits = bits_for(n);
     g->serial = g_serial.fetch_add(1);
     for (auto &e : g->ev) KC_HIP(hipEventCreate(&e));
+    for (auto &e : g->sev) KC_HIP(hipEventCreate(&e));
     KC_TRY(kc_dev_alloc((void **)&g->d_res, KC_RES_WORDS * sizeof(uint64_t), g->stream));
     if (!kc_pinned_scratch()) return kc_fail(KC_ENOMEM, "pinned host buffer");
     const uint32_t *ds = src, *dd = dst;
@@ -346,6 +349,14 @@ kc_status kc_last_tier_timings(const kc_graph *g, float *ms_wave, float *ms_work
     if (ms_wave) *ms_wave = g->t_tier[0];
     if (ms_workgroup) *ms_workgroup = g->t_tier[1];
     if (ms_scratch) *ms_scratch = g->t_tier[2];
+    return KC_OK;
+}
+
+kc_status kc_last_stage_timings(const kc_graph *g, float *ms_wave, float *ms_workgroup, float *ms_scratch) {
+    if (!g) return kc_fail(KC_EINVAL, "graph is NULL");
+    if (ms_wave) *ms_wave = g->t_stage_tier[0];
+    if (ms_workgroup) *ms_workgroup = g->t_stage_tier[1];
+    if (ms_scratch) *ms_scratch = g->t_stage_tier[2];
     return KC_OK;
 }
 

@@ -235,7 +235,9 @@ __device__ __forceinline__ void add_to(const CountParams &p, uint32_t gid, uint6
 // do not wait for each other's subtrees.
 // Rows of lanes >= s must be zero.
 // ============================================================================
-// NS = depth-first stack entries: counting ell-cliques uses ell - 3 of them.
+// NS = depth-first stack entries: counting ell-cliques uses ell - 3 of them, or
+// ell - 4 when a node that needs two more nodes counts the edges inside its
+// candidate set in place (INPLACE2 below); at least one.
 // Depth-first stack levels kept in registers; deeper stacks live in LDS (where
 // registers would spill).  The one-wave kernel keeps two levels, the
 // workgroup kernel two as well (three spill).
@@ -297,7 +299,12 @@ __device__ __forceinline__ uint32_t edges_inside(uint64_t P, const uint64_t *row
     return c;
 }
 
-template <int REGL, bool SPREAD3, int NS>
+// INPLACE2: a node that needs two more nodes counts the edges inside its candidate
+// set in place (one-wave tier: small, sparse local graphs, where this saves most of
+// the state machine's steps); otherwise it is pushed and its members are taken one
+// step each (workgroup tier: dense candidate sets, where the in-place loops leave
+// the other lanes idle).
+template <int REGL, bool SPREAD3, bool INPLACE2, int NS>
 __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int ell, uint64_t &acc) {
     static_assert(REGL >= LC_LDS_FROM, "levels neither in registers nor in LDS");
     const uint32_t lane = kc_lane();
@@ -428,6 +435,7 @@ __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int el
         }
         if (depth >= 0) {
             uint64_t cur = sget(depth);
+            const int rem = R - depth - 1;  // nodes still to choose after the next member
             if (cur == 0) {
                 --depth;
             } else {
@@ -435,9 +443,11 @@ __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int el
                 cur &= cur - 1;
                 sset(depth, cur);
                 const uint64_t child = cur & A.rows[v];
-                const int rem = R - depth - 1;  // nodes still to choose after v
                 if (rem == 1) {
                     acc += (uint64_t)__popcll(child);
+                } else if (INPLACE2 && rem == 2) {
+                    // the edges inside the child set, four members per step, in place
+                    acc += edges_inside(child, A.rows);
                 } else if ((int)__popcll(child) >= rem) {
                     ++depth;
                     sset(depth, child);
@@ -635,7 +645,7 @@ static_assert(offsetof(WaveStage, rows) == 0 && offsetof(LocalArea<1>, rows) == 
 template <int K>
 struct WaveSmem {
     union {
-        LocalArea<(K > 4 ? K - 4 : 1)> A;
+        LocalArea<(K > 5 ? K - 5 : 1)> A;
         WaveStage S;
     };
     uint32_t nb[64];      // the packed Gamma+ lists
@@ -877,7 +887,7 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
             continue;
         }
         wave_sync();
-        local_count<LC_REG_WAVE, true>(sm.A, d, K - 1, acc);
+        local_count<LC_REG_WAVE, true, true>(sm.A, d, K - 1, acc);
 
         if (p.per_root) {
             const uint64_t q = kc_wave_sum_checked(acc, &ovf);
@@ -1345,7 +1355,7 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                 }
                 if (pc <= 64) {
                     const uint32_t sN = compact_local(ri, lo0, W, bm, W, A);
-                    local_count<LC_REG_WG, false>(A, sN, K - 2, acc);
+                    local_count<LC_REG_WG, false, false>(A, sN, K - 2, acc);
                     return;
                 }
                 if (K >= 5 && p.local2 && pc <= 128) {
@@ -1402,7 +1412,7 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                         wave_sync();
                     } else if (cpc <= 64) {
                         const uint32_t sN = compact_local(nxt, clo, W, bm, W, A);
-                        local_count<LC_REG_WG, false>(A, sN, cn, acc);
+                        local_count<LC_REG_WG, false, false>(A, sN, cn, acc);
                     } else if (K >= 5 && p.local2 && cpc <= 128) {
                         const uint32_t sN = compact_local2(nxt, clo, W, bm, W, A2);
                         local_count2(A2, sN, cn, acc);
@@ -1509,7 +1519,7 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                         if (K > 4) {
                             A.rows[lane] = lrow;
                             wave_sync();
-                            local_count<LC_REG_WG, false>(A, S, K - 2, acc);
+                            local_count<LC_REG_WG, false, false>(A, S, K - 2, acc);
                         } else {
                             wave_sync();  // rs/rt are rewritten by the next pack
                         }
@@ -1951,8 +1961,9 @@ kc_status kc_stage(kc_graph *g, int wd) {
     kc_count_args a;
     a.k = 3;
     a.store = 1;
+    hipEvent_t sev[6] = {g->sev[0], g->sev[1], g->sev[2], g->sev[3], g->sev[4], g->sev[5]};
     KC_TRY(kc_count_launch(g, q, a, g->d_res, nullptr, 0, nullptr, gscr.as<uint64_t>(), slice_words, scratch_blocks,
-                           s, nullptr));
+                           s, sev[0] ? sev : nullptr));
     g->staged = 1;
     g->stage_wd = wd;
     return KC_OK;
@@ -2066,6 +2077,17 @@ kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_a
     return KC_OK;
 }
 
+// Tier kernel times of the staging pass that just ran (after a host synchronisation).
+static void stage_tier_times(kc_graph *g) {
+    float tt[3] = {0.f, 0.f, 0.f};
+    if (g->sev[0]) {
+        (void)hipEventElapsedTime(&tt[2], g->sev[0], g->sev[1]);
+        (void)hipEventElapsedTime(&tt[1], g->sev[1], g->sev[2]);
+        (void)hipEventElapsedTime(&tt[0], g->sev[4], g->sev[5]);
+    }
+    for (int t = 0; t < 3; ++t) g->t_stage_tier[t] = tt[t];
+}
+
 kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *total, int *overflow) {
     hipStream_t s = g->stream;
     const uint32_t dcap = kc_lds_dcap(g->device, a.k);
@@ -2098,6 +2120,7 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
         (void)hipEventElapsedTime(&t_sched, g->ev[0], g->ev[1]);
         kc_graph *gm = const_cast<kc_graph *>(g);
         for (int t = 0; t < 3; ++t) gm->t_tier[t] = 0.f;
+        stage_tier_times(gm);
         gm->t_schedule = t_sched;
         gm->t_count = 0.f;
         gm->t_total = t_sched;
@@ -2166,6 +2189,7 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
     (void)hipEventElapsedTime(&tt[0], g->ev[6], g->ev[7]);
     kc_graph *gm = const_cast<kc_graph *>(g);
     for (int t = 0; t < 3; ++t) gm->t_tier[t] = tt[t];
+    if (staged_now) stage_tier_times(gm);
     gm->t_schedule = t_sched;
     gm->t_count = t_count;
     gm->t_total = t_sched + t_count;

@@ -135,6 +135,8 @@ struct kc_graph {
     hipEvent_t fork = nullptr, join = nullptr;
     float t_schedule = 0.f, t_count = 0.f, t_total = 0.f;
     float t_tier[3] = {0.f, 0.f, 0.f};  // wave, workgroup, scratch kernels of the last count
+    hipEvent_t sev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // around the staging tiers
+    float t_stage_tier[3] = {0.f, 0.f, 0.f};  // wave, workgroup, scratch kernels of the last staging pass
 };
 
 // ----------------------------------------------------------------------------

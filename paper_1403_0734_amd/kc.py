@@ -25,7 +25,7 @@ EXPORTS = [
     "kc_count_batch", "kc_set_schedule", "kc_train_schedule", "kc_graph_info", "kc_get_csr",
     "kc_get_oriented", "kc_last_timings", "kc_graph_destroy", "kc_status_str",
     "kc_set_tuning", "kc_get_tuning", "kc_autotune", "kc_last_tier_timings", "kc_count_noalloc",
-    "kc_predict_work", "kc_mlp_step",
+    "kc_predict_work", "kc_mlp_step", "kc_last_stage_timings",
 ]
 
 
@@ -83,6 +83,8 @@ def load(path: str = LIB_PATH):
         "kc_autotune": (i32, [P, u32, i32, ctypes.c_char_p, ctypes.POINTER(kc_tuning)]),
         "kc_last_tier_timings": (i32, [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                        ctypes.POINTER(ctypes.c_float)]),
+        "kc_last_stage_timings": (i32, [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                        ctypes.POINTER(ctypes.c_float)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -230,6 +232,12 @@ def kc_last_timings(g: int):
 def kc_last_tier_timings(g: int):
     a, b, c = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
     check(load().kc_last_tier_timings(g, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "kc_last_tier_timings")
+    return a.value, b.value, c.value
+
+
+def kc_last_stage_timings(g: int):
+    a, b, c = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
+    check(load().kc_last_stage_timings(g, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "kc_last_stage_timings")
     return a.value, b.value, c.value
 
 

@@ -51,3 +51,16 @@ def test_null_arguments_rejected_without_device():
     with pytest.raises(K.KcError) as e:
         K.kc_count(None, 3)
     assert e.value.status == K.KC_EINVAL
+
+
+def test_peaks_library_exports_its_header():
+    """The peak microbenchmark library exports every kcp_ entry point its header
+    declares (no GPU needed to load it)."""
+    from paper_1403_0734_amd import peaks
+    text = open(os.path.join(ROOT, "include", "kc_peaks.h")).read()
+    names = sorted(set(re.findall(r"^\s*int\s+(kcp_\w+)\s*\(", text, re.M)))
+    assert names == sorted(peaks.EXPORTS)
+    lib = peaks.load()
+    for name in names:
+        assert hasattr(lib, name), name
+
