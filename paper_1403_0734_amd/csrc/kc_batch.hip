@@ -204,6 +204,7 @@ kc_status build_plan(kc_graph *const *gs, uint32_t num, int k, Plan &P) {
     if (!(sc && sc[0] == '0')) {
         KC_TRY(kc_stage_queue(&bg, P.q, wd, P.res.as<uint64_t>(), P.lrows, P.wbits, P.woff, P.cached));
     }
+    bg.stage_wd = wd;
     bg.lrows = P.cached ? P.lrows.as<uint64_t>() : nullptr;
     bg.wbits = P.cached ? P.wbits.as<uint64_t>() : nullptr;
     bg.woff = P.cached ? P.woff.as<uint64_t>() : nullptr;

@@ -155,6 +155,8 @@ struct CountParams {
     // staged G+(u) cache of the handle: wave-tier rows, larger roots' bitmaps
     uint64_t *lrows;
     uint64_t *wbits;
+    uint32_t stage_wd;          // roots of out-degree <= stage_wd keep rows at lrows, larger ones bitmaps
+    const uint64_t *wbits_raw;  // the staged bitmaps as staged (before any pair-sampling mask)
     uint32_t *wedges;           // staging: edges of each workgroup-tier G+(u), by rank (optional)
     unsigned long long *slots;  // 32 partial totals of a single-graph count (summed into *total)
     const uint64_t *woff;
@@ -304,26 +306,31 @@ __device__ __forceinline__ uint32_t edges_inside(uint64_t P, const uint64_t *row
 // the state machine's steps); otherwise it is pushed and its members are taken one
 // step each (workgroup tier: dense candidate sets, where the in-place loops leave
 // the other lanes idle).
+// First-node filter (fpart, fparts): only the cliques whose first (lowest) node has a
+// local index congruent to fpart modulo fparts are counted; (0, 1) counts all.  The
+// split items of the heaviest nodes (Section 7) share a node's subtree this way.
 template <int REGL, bool SPREAD3, bool INPLACE2, int NS>
-__device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int ell, uint64_t &acc) {
+__device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int ell, uint64_t &acc,
+                                            uint32_t fpart = 0, uint32_t fparts = 1) {
     static_assert(REGL >= LC_LDS_FROM, "levels neither in registers nor in LDS");
     const uint32_t lane = kc_lane();
     const uint64_t row = A.rows[lane];
+    const bool mine = fparts == 1 || lane % fparts == fpart;  // this lane's row may start cliques
     if (ell <= 1) {
-        if (lane == 0) acc += ell == 1 ? s : 1u;
+        if (lane == 0) acc += ell == 1 ? (fparts == 1 ? s : (s > fpart ? (s - fpart + fparts - 1) / fparts : 0u)) : 1u;
         return;
     }
     if (ell == 2) {
-        acc += (uint64_t)__popcll(row);
+        if (mine) acc += (uint64_t)__popcll(row);
         return;
     }
     const int R = ell - 2;  // nodes to choose inside an edge's candidate set
-    const uint32_t ce = (uint32_t)__popcll(row);
+    const uint32_t ce = mine ? (uint32_t)__popcll(row) : 0u;
     const uint32_t ei = kc_wave_incl_u32(ce);
     const uint32_t E = __shfl(ei, 63, 64);
     const bool listed = E <= LC_ELIST;
     if (listed) {
-        uint64_t r = row;
+        uint64_t r = mine ? row : 0ull;
         uint32_t pos = ei - ce;
         while (r) {
             A.elist[pos++] = (uint16_t)((lane << 8) | (uint32_t)__builtin_ctzll(r));
@@ -476,14 +483,17 @@ __device__ __forceinline__ uint32_t select_bit2(uint64_t w0, uint64_t w1, uint32
     return r < c0 ? select_bit(w0, r) : 64u + select_bit(w1, r - c0);
 }
 
+// (fpart, fparts): the first-node filter of local_count.
 template <int NS>
-__device__ __forceinline__ void local_count2(LocalArea2<NS> &A, uint32_t s, int ell, uint64_t &acc) {
+__device__ __forceinline__ void local_count2(LocalArea2<NS> &A, uint32_t s, int ell, uint64_t &acc,
+                                             uint32_t fpart = 0, uint32_t fparts = 1) {
     const uint32_t lane = kc_lane();
     // this lane's two rows 2*lane and 2*lane+1 (consecutive, so the task prefix stays ordered)
-    const uint32_t ca = (uint32_t)(__popcll(A.rows[2 * lane][0]) + __popcll(A.rows[2 * lane][1]));
-    const uint32_t cb = (uint32_t)(__popcll(A.rows[2 * lane + 1][0]) + __popcll(A.rows[2 * lane + 1][1]));
+    const bool ma = fparts == 1 || (2 * lane) % fparts == fpart, mb = fparts == 1 || (2 * lane + 1) % fparts == fpart;
+    const uint32_t ca = ma ? (uint32_t)(__popcll(A.rows[2 * lane][0]) + __popcll(A.rows[2 * lane][1])) : 0u;
+    const uint32_t cb = mb ? (uint32_t)(__popcll(A.rows[2 * lane + 1][0]) + __popcll(A.rows[2 * lane + 1][1])) : 0u;
     if (ell <= 1) {
-        if (lane == 0) acc += ell == 1 ? s : 1u;
+        if (lane == 0) acc += ell == 1 ? (fparts == 1 ? s : (s > fpart ? (s - fpart + fparts - 1) / fparts : 0u)) : 1u;
         return;
     }
     if (ell == 2) {
@@ -915,10 +925,7 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
 // Row i holds words (i+1)/64 .. W-1; its first word sits at
 // rowoff(i) = i*W - sum_{t=1}^{i} floor(t/64).
 // ============================================================================
-__host__ __device__ inline uint64_t tri_rowoff(uint64_t i, uint64_t W) {
-    const uint64_t q = i >> 6, r = i & 63;
-    return i * W - (64 * (q * (q - (q ? 1 : 0)) / 2) + q * (r + 1));
-}
+__host__ __device__ inline uint64_t tri_rowoff(uint64_t i, uint64_t W) { return kc_tri_rowoff(i, W); }
 __host__ __device__ inline uint64_t tri_words(uint64_t d) {
     const uint64_t W = (d + 63) / 64;
     return tri_rowoff(d, W);
@@ -1076,8 +1083,9 @@ __device__ __forceinline__ uint32_t compact_local2(const uint64_t *P, uint32_t l
 // Edges of G+(u) inside the node set C (words lo..W-1, absolute word index):
 // sum over members v of |C n row_v|.  Members are gathered 64 at a time into
 // mem (one per lane), each lane then intersects its member's row with C.
+// (fpart, fparts): only members v with v % fparts == fpart start an edge.
 __device__ __forceinline__ void wide_edges(const uint64_t *C, uint32_t lo, uint32_t W, const uint64_t *bm,
-                                           uint32_t *mem, uint64_t &acc) {
+                                           uint32_t *mem, uint64_t &acc, uint32_t fpart = 0, uint32_t fparts = 1) {
     const uint32_t lane = kc_lane();
     auto flush = [&](uint32_t k) {
         wave_sync();
@@ -1089,8 +1097,10 @@ __device__ __forceinline__ void wide_edges(const uint64_t *C, uint32_t lo, uint3
         wave_sync();
     };
     uint32_t cnt = 0;
+    uint64_t cls = ~0ull;  // members of the filter's class in this word
     for (uint32_t wb = lo; wb < W; ++wb) {
-        const uint64_t word = C[wb];
+        if (fparts > 1) cls = __ballot((64u * wb + lane) % fparts == fpart);
+        const uint64_t word = C[wb] & cls;
         if (!word) continue;
         const uint32_t nbits = (uint32_t)__popcll(word);
         const bool bit = (word >> lane) & 1ull;
@@ -1109,7 +1119,9 @@ __device__ __forceinline__ void wide_edges(const uint64_t *C, uint32_t lo, uint3
 
 // NW waves per block (4, 8 or 16): the waves share the root's bitmap, so a larger
 // block keeps more waves resident when one arena fills most of the LDS.
-template <int K, bool GLOBAL, int MODE, int NW>
+// L2: the item list holds two-level items (and roots that leave wide nodes to them);
+// without it the kernel carries none of that code or its registers.
+template <int K, bool GLOBAL, int MODE, int NW, bool L2>
 __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
     constexpr uint32_t WGT = NW * 64;
     extern __shared__ __align__(16) unsigned char smem_dyn[];
@@ -1157,12 +1169,27 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
             cn = (p.count - cb) < chunk ? (p.count - cb) : chunk;
             ci = 0;
         }
-        uint32_t u, part = 0, parts = 1;
+        // items (work_item in kc_internal.h): a root's first-level nodes part, part +
+        // parts, ...; or one first-level node v2 whose second-level nodes of class part2
+        // (mod parts2) are shared by the block's waves (two levels of splitting)
+        uint32_t u, part = 0, parts = 1, v2 = 0, part2 = 0, parts2 = 0, wide_t = 0;
+        bool skip_wide = false;
         if (p.items) {
             const uint64_t it = p.items[cb + ci];
             u = (uint32_t)(it >> 32);
-            part = (uint32_t)(it >> 16) & 0xFFFFu;
-            parts = (uint32_t)it & 0xFFFFu;
+            const uint32_t lo = (uint32_t)it;
+            if (L2 && (lo & KC_ITEM_LEVEL2)) {
+                v2 = lo >> 16;
+                part2 = (lo >> 7) & 127u;
+                parts2 = lo & 127u;
+            } else {
+                part = (lo >> 16) & 63u;
+                parts = lo & 0xFFu;
+                if (L2) {
+                    skip_wide = (lo & KC_ITEM_SKIP_WIDE) != 0;
+                    wide_t = lo >> 22;
+                }
+            }
         } else {
             u = p.queue[cb + ci];
         }
@@ -1177,7 +1204,9 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
             // G+(u) from the staged cache; colourings drop the edges they exclude
             W = (d + 63) / 64;
             words = tri_words(d);
-            const uint64_t *src = p.wbits + p.woff[u];
+            // a root at or below the one-wave limit (promoted to this tier by the learned
+            // schedule) keeps one row per node, which is its packed bitmap for d <= 64
+            const uint64_t *src = d <= p.stage_wd ? p.lrows + base : p.wbits + p.woff[u];
             for (uint64_t w = tid; w < words; w += WGT) bm[w] = src[w];
             if (p.colored) {
                 for (uint32_t t = tid; t < d; t += WGT) nb[t] = p.ocol[base + t];
@@ -1342,7 +1371,8 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
             // first-level nodes; a root split into `parts` items (Section 7: heavy
             // G+(u) shared by several reducers) takes the nodes part, part + parts,
             // part + 2 parts, ... in this item.  One node with a whole wave:
-            auto one_node = [&](const uint32_t i) {
+            // fpart, fparts: only second-level nodes of this class (filter of local_count)
+            auto one_node = [&](const uint32_t i, const uint32_t fpart, const uint32_t fparts) {
                 const uint32_t lo0 = (i + 1) >> 6;
                 const uint64_t *ri = bm_row(bm, i, W);
                 uint32_t pc = 0;
@@ -1350,17 +1380,17 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                 pc = kc_wave_sum_u32(pc);
                 if ((int)pc < K - 2) return;
                 if (K == 4) {
-                    wide_edges(ri, lo0, W, bm, A.members, acc);
+                    wide_edges(ri, lo0, W, bm, A.members, acc, fpart, fparts);
                     return;
                 }
                 if (pc <= 64) {
                     const uint32_t sN = compact_local(ri, lo0, W, bm, W, A);
-                    local_count<LC_REG_WG, false, false>(A, sN, K - 2, acc);
+                    local_count<LC_REG_WG, false, false>(A, sN, K - 2, acc, fpart, fparts);
                     return;
                 }
                 if (K >= 5 && p.local2 && pc <= 128) {
                     const uint32_t sN = compact_local2(ri, lo0, W, bm, W, A2);
-                    local_count2(A2, sN, K - 2, acc);
+                    local_count2(A2, sN, K - 2, acc, fpart, fparts);
                     return;
                 }
                 // Wide depth-first search.  stk[depth] holds the candidates not yet
@@ -1378,13 +1408,22 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                     int v = -1;
                     for (uint32_t wb = lo[depth]; wb < W; wb += 64) {
                         const uint32_t l = wb + lane;
-                        const uint64_t word = l < W ? cur[l] : 0ull;
+                        uint64_t word = l < W ? cur[l] : 0ull;
+                        if (depth == 0 && fparts > 1 && word) {
+                            // second-level nodes of the filter's class only: bits b of word l
+                            // with 64 l + b = fpart (mod fparts)
+                            uint64_t cls = 0;
+                            for (uint32_t b = (fpart + fparts - (64u * l) % fparts) % fparts; b < 64; b += fparts)
+                                cls |= 1ull << b;
+                            word &= cls;
+                        }
                         const uint64_t bal = __ballot(word != 0);
                         if (bal) {
                             const uint32_t fl = (uint32_t)__builtin_ctzll(bal);
                             const uint64_t wsel = __shfl(word, fl, 64);
-                            v = (int)((wb + fl) * 64 + (uint32_t)__builtin_ctzll(wsel));
-                            if (lane == fl) cur[l] = word & (word - 1);
+                            const uint32_t b = (uint32_t)__builtin_ctzll(wsel);
+                            v = (int)((wb + fl) * 64 + b);
+                            if (lane == fl) cur[l] &= ~(1ull << b);
                             lo[depth] = wb + fl;
                             break;
                         }
@@ -1422,7 +1461,11 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                     }
                 }
             };
-            if (K >= 4) {
+            if (L2 && K >= 4 && parts2) {
+                // one first-level node; its second-level nodes of class part2 (mod parts2)
+                // are dealt out to the block's waves
+                if constexpr (L2) one_node(v2, part2 + wave * parts2, parts2 * NW);
+            } else if (K >= 4) {
                 // Nodes are taken GRAB at a time.  Those with more than 64 candidates
                 // go one by one; the others are packed while their candidate sets
                 // sum to at most 64 nodes, side by side as the diagonal blocks of one
@@ -1454,13 +1497,24 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                         const uint64_t *ri = bm_row(bm, my_i, W);
                         for (uint32_t l = (my_i + 1) >> 6; l < W; ++l) my_pc += (uint32_t)__popcll(ri[l]);
                     }
-                    uint64_t big = __ballot(valid && my_pc > 64u);
+                    // Nodes whose candidate set held more than wide_t nodes when staged are
+                    // left to their two-level items.  The test reads the bitmap as staged,
+                    // as the item builder did: a colouring or pair mask may have shrunk the
+                    // set in LDS.
+                    bool mine = valid;
+                    if (L2 && skip_wide && valid) {
+                        const uint64_t *rr = p.wbits_raw + p.woff[u] + tri_rowoff(my_i, W) - ((my_i + 1) >> 6);
+                        uint32_t raw = 0;
+                        for (uint32_t l = (my_i + 1) >> 6; l < W; ++l) raw += (uint32_t)__popcll(rr[l]);
+                        mine = raw <= wide_t;
+                    }
+                    uint64_t big = __ballot(mine && my_pc > 64u);
                     while (big) {
                         const uint32_t t = (uint32_t)__builtin_ctzll(big);
                         big &= big - 1;
-                        one_node(__shfl(my_i, t, 64));
+                        one_node(__shfl(my_i, t, 64), 0u, 1u);
                     }
-                    uint64_t cm = __ballot(valid && my_pc >= (uint32_t)(K - 2) && my_pc <= 64u);
+                    uint64_t cm = __ballot(mine && my_pc >= (uint32_t)(K - 2) && my_pc <= 64u);
                     while (cm) {
                         const bool in = (cm >> lane) & 1ull;
                         const uint32_t v = in ? my_pc : 0u;
@@ -1533,7 +1587,7 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                     j = __shfl(j, 0, 64);
                     const uint32_t i = part + j * parts;
                     if (i >= d) break;
-                    one_node(i);
+                    one_node(i, 0u, 1u);
                 }
             }
         }
@@ -1553,7 +1607,7 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                 q = nq;
             }
             if (p.per_root) {
-                if (parts == 1) p.per_root[p.rank2id[u]] = q;
+                if (parts == 1 && (!L2 || (!skip_wide && !parts2))) p.per_root[p.rank2id[u]] = q;
                 else atomicAdd((unsigned long long *)&p.per_root[p.rank2id[u]], (unsigned long long)q);
             }
             const uint32_t gq = p.graph_of ? p.graph_of[u] : 0u;
@@ -1652,7 +1706,7 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
         p.gscratch = gscratch;
         p.slice_words = slice_words;
         p.dcap = q.max_d[2];
-        hipLaunchKernelGGL((k_count_wg<K, true, MODE, WAVES>), dim3(scratch_blocks), dim3(WG), 0, s, p);
+        hipLaunchKernelGGL((k_count_wg<K, true, MODE, WAVES, false>), dim3(scratch_blocks), dim3(WG), 0, s, p);
     }
     if (ev) (void)hipEventRecord(ev[1], s);
     if (q.count[1]) {
@@ -1666,21 +1720,27 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
         // LDS.  Measured: R-MAT 22 at k = 5, 1.98 s with four waves, 1.44 s with the
         // larger block; planted 4M at k = 8, 349 ms with two four-wave blocks per CU,
         // 570 ms with one 16-wave block.
-        const void *fn[3] = {(const void *)&k_count_wg<K, false, MODE, 4>, (const void *)&k_count_wg<K, false, MODE, 8>,
-                             (const void *)&k_count_wg<K, false, MODE, 16>};
+        const void *fn[3] = {(const void *)&k_count_wg<K, false, MODE, 4, false>,
+                             (const void *)&k_count_wg<K, false, MODE, 8, false>,
+                             (const void *)&k_count_wg<K, false, MODE, 16, false>};
+        const void *fn2[3] = {(const void *)&k_count_wg<K, false, MODE, 4, true>,
+                              (const void *)&k_count_wg<K, false, MODE, 8, true>,
+                              (const void *)&k_count_wg<K, false, MODE, 16, true>};
         const int nws[3] = {4, 8, 16};
         // static LDS of each block shape as compiled (the per-wave arrays grow with it),
         // looked up once; the attribute caps the dynamic LDS of later launches (graph
         // replays included)
         static size_t stat[3] = {0, 0, 0};
         for (int i = 0; i < 3; ++i) {
-            if (!stat[i]) {
+            if (!stat[i]) {  // the same static arrays with and without L2
                 hipFuncAttributes fa;
                 stat[i] = hipFuncGetAttributes(&fa, fn[i]) == hipSuccess ? fa.sharedSizeBytes
                                                                           : wg_static_lds(K, nws[i]) + 1024;
             }
-            if (stat[i] < di.lds_max)
+            if (stat[i] < di.lds_max) {
                 (void)hipFuncSetAttribute(fn[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)(di.lds_max - stat[i]));
+                (void)hipFuncSetAttribute(fn2[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)(di.lds_max - stat[i]));
+            }
         }
         struct Shape {
             int idx;
@@ -1698,7 +1758,9 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
                 // no more than are resident at once (registers): a block launched past
                 // that starts only when the queue is spent
                 int occ = 0;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn[i], nw * 64, L.bytes) == hipSuccess && occ > 0 &&
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, q.wg_l2 ? fn2[i] : fn[i], nw * 64, L.bytes) ==
+                        hipSuccess &&
+                    occ > 0 &&
                     (uint32_t)occ < per_cu)
                     per_cu = (uint32_t)occ;
                 if (per_cu * (uint32_t)nw > 32u) per_cu = 32u / (uint32_t)nw;
@@ -1723,12 +1785,19 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
             const WgLayout L = wg_layout(p.dcap, K, nw);
             uint32_t blocks = (uint32_t)di.cus * sh.per_cu;
             if (blocks > count) blocks = count;
-            if (nw == 16)
-                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 16>), dim3(blocks), dim3(1024), L.bytes, s, p);
+            const bool l2 = items && q.wg_l2;
+            if (nw == 16 && l2)
+                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 16, true>), dim3(blocks), dim3(1024), L.bytes, s, p);
+            else if (nw == 16)
+                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 16, false>), dim3(blocks), dim3(1024), L.bytes, s, p);
+            else if (nw == 8 && l2)
+                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 8, true>), dim3(blocks), dim3(512), L.bytes, s, p);
             else if (nw == 8)
-                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 8>), dim3(blocks), dim3(512), L.bytes, s, p);
+                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 8, false>), dim3(blocks), dim3(512), L.bytes, s, p);
+            else if (l2)
+                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 4, true>), dim3(blocks), dim3(256), L.bytes, s, p);
             else
-                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 4>), dim3(blocks), dim3(256), L.bytes, s, p);
+                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 4, false>), dim3(blocks), dim3(256), L.bytes, s, p);
         };
         if (q.wg_items) {
             launch_wg(q.ptr[1], q.wg_item_count, q.wg_items, cursors + 1, q.max_d[1]);
@@ -1884,6 +1953,7 @@ kc_status kc_stage_queue(const kc_graph *g, const kc_queue &q, int wd, uint64_t 
     gs.lrows = lrows.as<uint64_t>();
     gs.wbits = wbits.as<uint64_t>();
     gs.woff = woff.as<uint64_t>();
+    gs.stage_wd = wd;
     kc_tmp gscr;
     size_t slice_words = 0;
     uint32_t scratch_blocks = 0;
@@ -2038,6 +2108,8 @@ kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_a
     p.gtotals = gtotals;
     p.lrows = g->lrows;
     p.wbits = g->wbits;
+    p.stage_wd = (uint32_t)g->stage_wd;
+    p.wbits_raw = g->wbits_raw ? g->wbits_raw : g->wbits;
     p.woff = g->woff;
     p.wedges = g->wedges;
     uint32_t *cursors = (uint32_t *)(res + 2);
@@ -2159,6 +2231,7 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
         view = *g;
         view.lrows = mrows.as<uint64_t>();
         view.wbits = mbits.as<uint64_t>();
+        view.wbits_raw = g->wbits;  // work items were split on the bitmaps as staged
         gc = &view;
     }
     // the second stream (one-wave tier beside the others, k >= 7) is created on first use,

@@ -94,6 +94,7 @@ struct kc_graph {
         uint32_t *queue = nullptr;   // scratch, workgroup, one-wave tier (with the degree queue's tail)
         uint64_t *items = nullptr;   // workgroup tier as split items (k >= 5)
         uint32_t item_count = 0;
+        bool l2 = false;             // the items include two-level items
         uint32_t count[3] = {0, 0, 0}, max_d[3] = {0, 0, 0};  // kc_queue order: wave, workgroup, scratch
     } lq[KC_KMAX + 1];
 
@@ -117,6 +118,7 @@ struct kc_graph {
     int stage_wd = 0;
     uint64_t stage_words = 0;  // words at wbits
     uint64_t *lrows = nullptr, *wbits = nullptr, *woff = nullptr;
+    const uint64_t *wbits_raw = nullptr;  // set in a masked view: the bitmaps as staged
 
     // Workgroup-tier items for counts from k = 5 on (degree policy, staged
     // handles): the tier's roots by edges of G+(u), heaviest first, the heaviest
@@ -125,6 +127,7 @@ struct kc_graph {
     int wq_ready = 0;
     uint32_t wq_first = 0, wq_roots = 0, wq_count = 0;
     uint64_t *wq = nullptr;
+    bool wq_l2 = false;          // wq holds two-level items
     uint32_t *wedges = nullptr;  // edges of G+(u) by rank, written when staging (roots above stage_wd)
 
     uint64_t serial = 0;  // unique per handle (batch plans are keyed by it)
@@ -215,8 +218,9 @@ static_assert(KC_MLP_PARAMS == KC_MLP_IN * KC_MLP_H + KC_MLP_H + KC_MLP_H * KC_M
 struct kc_queue {
     kc_tmp buf;                // storage when the queue is built per call
     kc_tmp items_buf;
-    const uint64_t *wg_items = nullptr;  // workgroup tier as split items (rank << 32 | part << 16 | parts)
+    const uint64_t *wg_items = nullptr;  // workgroup tier as split items (see KC_ITEM_LEVEL2 below)
     uint32_t wg_item_count = 0;
+    bool wg_l2 = false;                  // the items include two-level items
     const uint32_t *ptr[3];    // root ranks of each tier (wave, workgroup, scratch), heaviest first
     uint32_t count[3];         // roots per tier
     uint32_t max_d[3];         // largest out-degree in each tier
@@ -228,6 +232,25 @@ struct kc_queue {
 // no_alloc: degree policy only, from the handle's degree queue and work items as they
 // already are (KC_ESTATE when the degree queue is not built); nothing is allocated,
 // and heavy roots stay whole when the handle holds no work items for this tier.
+// Packed upper-triangular bitmap of G+(u) with d nodes and W = ceil(d / 64) words per
+// row: row i holds words floor((i+1)/64) .. W-1 and starts at word
+// i*W - sum_{t=1}^{i} floor(t/64) of the root's bitmap.
+__host__ __device__ inline uint64_t kc_tri_rowoff(uint64_t i, uint64_t W) {
+    const uint64_t q = i >> 6, r = i & 63;
+    return i * W - (64 * (q * (q - (q ? 1 : 0)) / 2) + q * (r + 1));
+}
+
+// Workgroup-tier work items (64 bits): the root's rank in the high half, and in the
+// low half either
+//   t << 22 | part << 16 | parts (1..64) [| KC_ITEM_SKIP_WIDE]: the root's first-level
+//       nodes part, part + parts, ...; with the flag, those whose candidate set held
+//       more than t (> KC_ITEM_WIDE) nodes when staged are left to two-level items;
+//   v << 16 | KC_ITEM_LEVEL2 | part2 << 7 | parts2 (2..127): first-level node v only,
+//       the cliques whose second-level node index is part2 mod parts2.
+// A rank of 0xFFFFFFFF is padding.
+constexpr uint32_t KC_ITEM_LEVEL2 = 1u << 15;
+constexpr uint32_t KC_ITEM_SKIP_WIDE = 1u << 14;
+constexpr uint32_t KC_ITEM_WIDE = 128;
 kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_max, kc_queue &q,
                          bool no_alloc = false);
 size_t kc_scratch_slice_words(uint32_t dmax, int k);

@@ -124,6 +124,7 @@ struct EstEdges {
     const uint32_t *q;
     const uint32_t *wedges;
     const uint64_t *optr;
+    const uint64_t *wbits, *woff;  // the staged bitmaps (two-level items), or null
     __device__ uint32_t rank(size_t i) const { return q[i]; }
     __device__ uint64_t outdeg(size_t i) const { return optr[q[i] + 1] - optr[q[i]]; }
     __device__ uint32_t est(size_t i) const { return root_est(wedges[q[i]], outdeg(i)); }
@@ -134,6 +135,7 @@ struct EstEdges {
 struct EstLearned {
     const uint64_t *keys;
     const uint64_t *optr;
+    const uint64_t *wbits, *woff;  // the staged bitmaps (two-level items), or null
     __device__ uint32_t rank(size_t i) const { return (uint32_t)keys[i]; }
     __device__ uint64_t outdeg(size_t i) const { return optr[rank(i) + 1] - optr[rank(i)]; }
     __device__ uint32_t est(size_t i) const {
@@ -180,8 +182,139 @@ __global__ void k_root_parts(Est E, uint32_t cnt, WqAux *a, uint32_t *parts) {
 
 constexpr uint32_t WQ_SKIP = 0xFFFFFFFFu;
 
+// Two-level items (Section 7, the further split of the heaviest sub-problems): in a
+// root cut into several items, every first-level node v whose candidate set holds more
+// than KC_ITEM_WIDE nodes gets parts2 items of its own, ceil(est_v / target) with est_v
+// the root's estimate times pc_v^2 / sum over the root's nodes of pc^2 (pc = candidate
+// set size); the root's first-level items then skip those nodes.  One block per root:
+// n2[i] = two-level items of root i (0 for roots that are not split).
+constexpr int L2T = 256;
+// Per root: the split threshold t (nodes whose candidate set holds more than t nodes
+// get two-level items: est_v = est * pc^2 / S2 >= 2 target, i.e. pc >= sqrt(2 target
+// S2 / est); at least KC_ITEM_WIDE + 1, the wide search's nodes; 1023 = none) and the
+// items of one such node, ceil(est_v / target) in 2..127.  force (KC_LEVEL2=2) splits
+// every wide node in two at least.
+__device__ __forceinline__ uint32_t level2_threshold(double est, double S2, double target, bool force) {
+    if (force) return KC_ITEM_WIDE;
+    if (est <= 0.0) return 1023u;
+    const double t = ceil(sqrt(2.0 * target * S2 / est));
+    if (t >= 1023.0) return 1023u;
+    return t <= (double)KC_ITEM_WIDE ? KC_ITEM_WIDE : (uint32_t)t;
+}
+__device__ __forceinline__ uint32_t level2_parts(double est, double S2, double target, uint32_t pc, bool force) {
+    double np = S2 > 0.0 ? ceil(est * (double)pc * (double)pc / S2 / target) : 2.0;
+    np = np < 2.0 ? 2.0 : (np > 127.0 ? 127.0 : np);
+    (void)force;
+    return (uint32_t)np;
+}
+
 template <class Est>
-__global__ void k_emit_items(Est E, const uint32_t *parts, uint32_t cnt, WqAux *a, uint32_t bound, uint64_t *items) {
+__global__ void __launch_bounds__(L2T) k_level2_count(Est E, const uint32_t *parts, uint32_t cnt, const WqAux *a,
+                                                     bool force, uint32_t *n2, uint32_t *thr) {
+    __shared__ double s_sum[L2T / 64];
+    __shared__ uint32_t s_cnt[L2T / 64];
+    const uint32_t i = blockIdx.x;
+    if (i >= cnt) return;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    // a wide node needs more than KC_ITEM_WIDE later nodes, so the root more than
+    // KC_ITEM_WIDE + 1 nodes: such roots keep a packed bitmap (above the one-wave limit)
+    const uint32_t d = (uint32_t)E.outdeg(i), W = (d + 63) / 64;
+    if (parts[i] < 2 || !E.wbits || d <= KC_ITEM_WIDE + 1) {
+        if (tid == 0) {
+            n2[i] = 0;
+            thr[i] = 1023u;
+        }
+        return;
+    }
+    const uint32_t u = E.rank(i);
+    const uint64_t *bm = E.wbits + E.woff[u];
+    auto pc_of = [&](uint32_t j) {
+        const uint64_t *rj = bm + kc_tri_rowoff(j, W) - ((j + 1) >> 6);
+        uint32_t c = 0;
+        for (uint32_t l = (j + 1) >> 6; l < W; ++l) c += (uint32_t)__popcll(rj[l]);
+        return c;
+    };
+    double sq = 0.0;
+    for (uint32_t j = tid; j < d; j += L2T) {
+        const double c = (double)pc_of(j);
+        sq += c * c;
+    }
+    for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off, 64);
+    if (lane == 0) s_sum[wave] = sq;
+    __syncthreads();
+    double S2 = 0.0;
+    for (int w = 0; w < L2T / 64; ++w) S2 += s_sum[w];
+    const double tot = a->sum;
+    double target = 4.0 * tot / (double)cnt;
+    if (tot / 1024.0 < target) target = tot / 1024.0;
+    if (target < 1.0) target = 1.0;
+    const double est = (double)E.est(i);
+    const uint32_t t = level2_threshold(est, S2, target, force);
+    uint32_t items = 0;
+    for (uint32_t j = tid; j < d; j += L2T) {
+        const uint32_t c = pc_of(j);
+        if (c > t) items += level2_parts(est, S2, target, c, force);
+    }
+    items = kc_wave_sum_u32(items);
+    if (lane == 0) s_cnt[wave] = items;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t sum = 0;
+        for (int w = 0; w < L2T / 64; ++w) sum += s_cnt[w];
+        n2[i] = sum;
+        thr[i] = sum ? t : 1023u;
+    }
+}
+
+// The two-level items of root i at items[off2[i] ..), in node order.
+template <class Est>
+__global__ void __launch_bounds__(L2T) k_level2_emit(Est E, const uint32_t *parts, uint32_t cnt, const WqAux *a,
+                                                    bool force, const uint32_t *n2, const uint32_t *off2,
+                                                    const uint32_t *thr, uint64_t *items) {
+    __shared__ double s_sum[L2T / 64];
+    __shared__ uint32_t s_pos;
+    const uint32_t i = blockIdx.x;
+    if (i >= cnt || n2[i] == 0) return;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const uint32_t u = E.rank(i);
+    const uint32_t d = (uint32_t)E.outdeg(i), W = (d + 63) / 64;
+    const uint64_t *bm = E.wbits + E.woff[u];
+    auto pc_of = [&](uint32_t j) {
+        const uint64_t *rj = bm + kc_tri_rowoff(j, W) - ((j + 1) >> 6);
+        uint32_t c = 0;
+        for (uint32_t l = (j + 1) >> 6; l < W; ++l) c += (uint32_t)__popcll(rj[l]);
+        return c;
+    };
+    double sq = 0.0;
+    for (uint32_t j = tid; j < d; j += L2T) {
+        const double c = (double)pc_of(j);
+        sq += c * c;
+    }
+    for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off, 64);
+    if (lane == 0) s_sum[wave] = sq;
+    if (tid == 0) s_pos = 0;
+    __syncthreads();
+    double S2 = 0.0;
+    for (int w = 0; w < L2T / 64; ++w) S2 += s_sum[w];
+    const double tot = a->sum;
+    double target = 4.0 * tot / (double)cnt;
+    if (tot / 1024.0 < target) target = tot / 1024.0;
+    if (target < 1.0) target = 1.0;
+    const double est = (double)E.est(i);
+    const uint32_t t = thr[i];
+    for (uint32_t j = tid; j < d; j += L2T) {
+        const uint32_t c = pc_of(j);
+        if (c <= t) continue;
+        const uint32_t m = level2_parts(est, S2, target, c, force);
+        const uint32_t at = off2[i] + atomicAdd(&s_pos, m);
+        for (uint32_t p2 = 0; p2 < m; ++p2)
+            items[at + p2] = ((uint64_t)u << 32) | ((uint64_t)j << 16) | KC_ITEM_LEVEL2 | ((uint64_t)p2 << 7) | m;
+    }
+}
+
+template <class Est>
+__global__ void k_emit_items(Est E, const uint32_t *parts, const uint32_t *n2, const uint32_t *thr, uint32_t cnt,
+                             WqAux *a, uint32_t bound, uint64_t *items) {
     __shared__ uint32_t base[256];
     __shared__ uint32_t s_total;
     const uint32_t tid = threadIdx.x;
@@ -202,8 +335,9 @@ __global__ void k_emit_items(Est E, const uint32_t *parts, uint32_t cnt, WqAux *
     for (size_t i = (size_t)blockIdx.x * blockDim.x + tid; i < cnt; i += stride) {
         const uint32_t u = E.rank(i), b = est_bucket(E.est(i)), np = parts[i];
         const uint32_t off = base[b] + atomicAdd(&a->bcur[b], np);
+        const uint64_t flag = n2 && n2[i] ? (KC_ITEM_SKIP_WIDE | ((uint64_t)thr[i] << 22)) : 0u;
         for (uint32_t pt = 0; pt < np; ++pt)
-            if (off + pt < bound) items[off + pt] = ((uint64_t)u << 32) | ((uint64_t)pt << 16) | (uint64_t)np;
+            if (off + pt < bound) items[off + pt] = ((uint64_t)u << 32) | ((uint64_t)pt << 16) | flag | (uint64_t)np;
     }
     for (size_t x = s_total + (size_t)blockIdx.x * blockDim.x + tid; x < bound; x += stride)
         items[x] = (uint64_t)WQ_SKIP << 32;
@@ -215,22 +349,52 @@ inline uint32_t work_items_bound(uint32_t cnt) {
     return cnt + extra + 1;
 }
 
-// Items of cnt roots into a new device list (owned by the caller, bound entries).
+// Items of cnt roots into a new device list (owned by the caller, *count entries):
+// the two-level items of the heaviest nodes first (when the staged bitmaps are given
+// and KC_LEVEL2 is not 0), then the roots' first-level items in estimate order,
+// padded to their bound.
 template <class Est>
-kc_status build_items(const Est &E, uint32_t cnt, hipStream_t s, uint64_t **items, uint32_t *bound_out) {
+kc_status build_items(const Est &E, uint32_t cnt, hipStream_t s, uint64_t **items, uint32_t *count, bool *l2out) {
     const uint32_t bound = work_items_bound(cnt);
-    kc_tmp aux, parts;
+    kc_tmp aux, parts, n2, off2, tot2;
     KC_TRY(kc_tmp_alloc(aux, sizeof(WqAux), s));
     KC_TRY(kc_tmp_alloc(parts, (size_t)cnt * 4, s));
-    KC_TRY(kc_dev_alloc((void **)items, (size_t)bound * 8, s));
     WqAux *a = aux.as<WqAux>();
     hipLaunchKernelGGL(k_wq_clear, dim3(1), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_est_sum<Est>, dim3(grid_for(cnt)), dim3(T), 0, s, E, cnt, a);
     hipLaunchKernelGGL(k_root_parts<Est>, dim3(grid_for(cnt)), dim3(T), 0, s, E, cnt, a, parts.as<uint32_t>());
-    hipLaunchKernelGGL(k_emit_items<Est>, dim3(grid_for(bound)), dim3(T), 0, s, E,
-                       (const uint32_t *)parts.as<uint32_t>(), cnt, a, bound, *items);
     KC_HIP(hipGetLastError());
-    *bound_out = bound;
+    uint32_t N2 = 0;
+    // KC_LEVEL2: 0 no two-level items, 2 every wide node of a split root split (tests)
+    const char *l2 = getenv("KC_LEVEL2");
+    const bool level2 = E.wbits && !(l2 && l2[0] == '0') && cnt;
+    const bool force = l2 && l2[0] == '2';
+    kc_tmp thr;
+    if (level2) {
+        KC_TRY(kc_tmp_alloc(n2, (size_t)cnt * 4, s));
+        KC_TRY(kc_tmp_alloc(thr, (size_t)cnt * 4, s));
+        KC_TRY(kc_tmp_alloc(off2, (size_t)cnt * 4, s));
+        KC_TRY(kc_tmp_alloc(tot2, 4, s));
+        hipLaunchKernelGGL(k_level2_count<Est>, dim3(cnt), dim3(L2T), 0, s, E, (const uint32_t *)parts.as<uint32_t>(),
+                           cnt, (const WqAux *)a, force, n2.as<uint32_t>(), thr.as<uint32_t>());
+        KC_HIP(hipGetLastError());
+        KC_TRY(kc_scan_excl_u32(n2.as<uint32_t>(), off2.as<uint32_t>(), cnt, tot2.as<uint32_t>(), s));
+        uint32_t *h = (uint32_t *)kc_pinned_scratch();
+        KC_HIP(hipMemcpyAsync(h, tot2.p, 4, hipMemcpyDeviceToHost, s));
+        KC_TRY(kc_sync(s));
+        N2 = h[0];
+    }
+    KC_TRY(kc_dev_alloc((void **)items, ((size_t)bound + N2) * 8, s));
+    if (N2)
+        hipLaunchKernelGGL(k_level2_emit<Est>, dim3(cnt), dim3(L2T), 0, s, E, (const uint32_t *)parts.as<uint32_t>(),
+                           cnt, (const WqAux *)a, force, (const uint32_t *)n2.as<uint32_t>(),
+                           (const uint32_t *)off2.as<uint32_t>(), (const uint32_t *)thr.as<uint32_t>(), *items);
+    hipLaunchKernelGGL(k_emit_items<Est>, dim3(grid_for(bound)), dim3(T), 0, s, E,
+                       (const uint32_t *)parts.as<uint32_t>(), level2 ? (const uint32_t *)n2.as<uint32_t>() : nullptr,
+                       level2 ? (const uint32_t *)thr.as<uint32_t>() : nullptr, cnt, a, bound, *items + N2);
+    KC_HIP(hipGetLastError());
+    *count = bound + N2;
+    *l2out = N2 > 0;
     return KC_OK;
 }
 
@@ -240,9 +404,9 @@ kc_status build_work_items(kc_graph *g, uint32_t first, uint32_t cnt) {
     g->wq = nullptr;
     g->wq_count = 0;
     g->wq_ready = 0;
-    EstEdges E{g->dq + first, g->wedges, g->optr};
+    EstEdges E{g->dq + first, g->wedges, g->optr, g->wbits, g->woff};
     uint32_t bound = 0;
-    KC_TRY(build_items(E, cnt, s, &g->wq, &bound));
+    KC_TRY(build_items(E, cnt, s, &g->wq, &bound, &g->wq_l2));
     g->wq_count = bound;
     g->wq_first = first;
     g->wq_roots = cnt;
@@ -375,8 +539,9 @@ static kc_status build_learned(kc_graph *g, int k, uint32_t wd, uint32_t dcap, k
         if (hist[d]) wmax = d > wmax ? d : wmax;
     L.max_d[0] = wmax;
     if (k >= 5 && L.count[1]) {
-        EstLearned E{keys.as<uint64_t>() + L.count[2], g->optr};
-        KC_TRY(build_items(E, L.count[1], s, &L.items, &L.item_count));
+        const bool bits = g->staged == 1 && g->stage_wd == (int)wd && g->wbits;
+        EstLearned E{keys.as<uint64_t>() + L.count[2], g->optr, bits ? g->wbits : nullptr, bits ? g->woff : nullptr};
+        KC_TRY(build_items(E, L.count[1], s, &L.items, &L.item_count, &L.l2));
     }
     L.wd = (int)wd;
     L.dcap = dcap;
@@ -416,6 +581,7 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
         }
         q.wg_items = L.items;
         q.wg_item_count = L.items ? L.item_count : 0;
+        q.wg_l2 = L.l2;
         q.wg_ncls = 0;
         return KC_OK;
     }
@@ -478,6 +644,7 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
             if (!have) KC_TRY(build_work_items(gm, first, q.count[1]));
             q.wg_items = g->wq;
             q.wg_item_count = g->wq_count;
+            q.wg_l2 = g->wq_l2;
             return KC_OK;
         }
         if (no_alloc) return KC_OK;

@@ -115,10 +115,13 @@ def test_tier_boundaries_complete_graphs():
         _close(h)
 
 
-def test_wide_search_closed_forms():
+@pytest.mark.parametrize("level2", ["1", "2"])
+def test_wide_search_closed_forms(monkeypatch, level2):
     """First-level candidate sets above 128 nodes (the wide depth-first search of the
     workgroup tier, from k = 5): K_400 and K_300 against C(n, k), and a complete
-    multipartite graph against the elementary symmetric polynomial of its parts."""
+    multipartite graph against the elementary symmetric polynomial of its parts; with
+    two-level items where the estimate asks for them (1) and for every wide node (2)."""
+    monkeypatch.setenv("KC_LEVEL2", level2)
     for n, ks in [(400, [5]), (300, [6])]:
         h = device_graph(S.complete(n))
         for k in ks:
@@ -132,16 +135,25 @@ def test_wide_search_closed_forms():
     _close(h)
 
 
-def test_wide_search_dense_random():
+@pytest.mark.parametrize("level2", ["1", "0", "2"])
+def test_wide_search_dense_random(monkeypatch, level2):
     """A dense G(500, 0.6): out-degrees up to about 275, first-level candidate sets of
-    about 165 nodes; totals and per-root counts at k = 5 against the oracle."""
+    about 165 nodes; totals and per-root counts at k = 5 against the oracle, with the
+    heaviest first-level nodes split into two-level items (Section 7) where the estimate
+    asks for them (1), never (0), and for every wide node (2)."""
+    monkeypatch.setenv("KC_LEVEL2", level2)
     el = S.random_graph(500, 0.6, 8)
     og = O.OracleGraph.from_edgelist(el)
     h = device_graph(el)
-    announce("G(500, 0.6) k=5")
+    announce(f"G(500, 0.6) k=5 level2={level2}")
     assert K.kc_count(h, 5) == og.count(5)
     c, _ = per_root(h, el.n, 5)
     assert np.array_equal(c, og.count_per_root(5))
+    for scheme in (K.KC_COLOR_PER_ROOT, K.KC_COLOR_GLOBAL):
+        e = K.kc_count_colored(h, 5, 2, 3, scheme)
+        assert e.raw == og.count_colored(5, 2, 3, scheme), scheme
+    e = K.kc_count_pair_sampled(h, 5, 0.5, 4)
+    assert e.raw == og.count_pair_sampled(5, 0.5, 4)
     _close(h)
 
 

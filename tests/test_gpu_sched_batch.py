@@ -70,6 +70,38 @@ def test_learned_schedule_counts_equal(stream, tmp_path):
         K.kc_graph_destroy(g)
 
 
+@pytest.mark.parametrize("cache", ["1", "0"])
+def test_learned_promotion_of_every_candidate(stream, tmp_path, monkeypatch, cache):
+    """With a promotion threshold of 0 the learned schedule moves every one-wave root it
+    considers into the workgroup tier, whose cached path then reads their staged rows
+    (not packed bitmaps); a dense G(500, 0.6) adds wide first-level nodes, each split
+    into two-level items of the learned estimate.  Counts, per-root counts and colourings against the
+    oracle, staged once or per call."""
+    monkeypatch.setenv("KC_STAGE_CACHE", cache)
+    monkeypatch.setenv("KC_PROMOTE_LOGWORK", "0")
+    monkeypatch.setenv("KC_LEVEL2", "2")
+    train = [graph_on(el, stream) for el in training_graphs()[:2]]
+    wpath = str(tmp_path / "w.bin")
+    K.kc_train_schedule(train, 6, 5, 3, wpath)
+    for g in train:
+        K.kc_graph_destroy(g)
+    for el in [S.planted_small(3000, 0.004, [list(range(i, i + 25)) for i in range(0, 2500, 500)], 9),
+               S.random_graph(500, 0.6, 8)]:
+        og = O.OracleGraph.from_edgelist(el)
+        h = graph_on(el, stream)
+        K.kc_set_schedule(h, K.KC_SCHED_LEARNED, wpath)
+        ks = [k for k in range(3, 9) if k < 6 or el.n != 500]
+        for k in ks:
+            announce(f"learned, all promoted, cache={cache} {el.name} k={k}")
+            assert K.kc_count(h, k) == og.count(k), (el.name, k)
+        k = ks[-1]
+        c, _ = per_root(h, el.n, k)
+        assert np.array_equal(c, og.count_per_root(k)), (el.name, k)
+        e = K.kc_count_colored(h, 5, 3, 8, K.KC_COLOR_PER_ROOT)
+        assert e.raw == og.count_colored(5, 3, 8, O.COLOR_PER_ROOT)
+        K.kc_graph_destroy(h)
+
+
 def test_learned_schedule_on_held_out_graph(stream, tmp_path):
     """A schedule trained on other graphs: counts and work labels stay exact."""
     train = [graph_on(el, stream) for el in training_graphs()]
