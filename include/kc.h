@@ -138,6 +138,18 @@ kc_status kc_count_pair_sampled(const kc_graph *g, int32_t k, double p, uint64_t
  * unpruned depth-first count performs.  3 <= k <= KC_KMAX. */
 kc_status kc_count_per_root(const kc_graph *g, int32_t k, uint64_t *dev_counts, uint64_t *dev_work);
 
+/* Per-node clique-membership counts (Section 3, the remark after the round-3
+ * reducers: a reducer can report, per node, the cliques of its sub-problem that
+ * contain it): dev_counts[v] = the number of k-cliques that contain v, for every
+ * node v, indexed by original id, in the caller's device array of n uint64
+ * (overwritten; the call returns when it is written).  Sums to k * q_k.
+ * 1 <= k <= KC_KMAX (k = 1: 1 each; k = 2: the degree).  For k >= 3 the local
+ * graphs are read from the handle's staged G+(u) cache (built here if absent):
+ * KC_ENOMEM when the cache is not kept; KC_EOVERFLOW when a count needs more than
+ * 64 bits; KC_EINVAL when the largest out-degree needs more LDS per wave than a
+ * workgroup has ((k - 2) * ceil(d / 64) * 8 bytes). */
+kc_status kc_count_per_node(const kc_graph *g, int32_t k, uint64_t *dev_counts);
+
 /* Exact q_k (3 <= k <= KC_KMAX) of num graphs at once; q_out[i] is the count of gs[i].
  * The graphs are laid side by side on the device as one disjoint union and counted
  * by the persistent tier kernels from one work queue (ordered by tier, graph and

@@ -75,6 +75,8 @@ def _load():
             "kco_count_pair_sampled": (i32, [P, i32, u64, u64, i32, P]),
             "kco_work_root": (i32, [P, u32, i32, P, P]),
             "kco_work_per_root": (i32, [P, i32, i32, P, P]),
+            "kco_count_per_node": (i32, [P, i32, i32, P]),
+            "kco_count_node": (i32, [P, u32, i32, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -247,6 +249,20 @@ class OracleGraph:
         b = np.empty(self.n, np.uint64)
         _check(_load().kco_work_per_root(self._h, k, threads, _p(a), _p(b)), "work_per_root")
         return a, b
+
+
+    def count_per_node(self, k: int, threads: int = 0) -> np.ndarray:
+        """k-cliques containing each node (by original id), summed over the roots'
+        sub-problems (Section 3, remark after the round-3 reducers)."""
+        out = np.empty(self.n, np.uint64)
+        _check(_load().kco_count_per_node(self._h, k, threads, _p(out)), f"count_per_node(k={k})")
+        return out
+
+    def count_node(self, v: int, k: int) -> int:
+        """k-cliques containing v, as the (k-1)-cliques inside its neighbourhood."""
+        q = np.zeros(1, np.uint64)
+        _check(_load().kco_count_node(self._h, v, k, _p(q)), f"count_node(v={v},k={k})")
+        return int(q[0])
 
 
 def scale_exponent(k: int, scheme: int) -> int:

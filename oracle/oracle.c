@@ -24,6 +24,9 @@
  *     scale is c^(k-1).
  *   - Per-root intersection work (the paper instruments sub-problem sizes,
  *     Section 4): W(u, k) = sum_{l=1}^{k-2} c_l(G+(u)).
+ *   - Per-node clique-membership counts (Section 3, the remark after the round-3
+ *     reducers): the k-cliques containing each node, as the sum over roots of the
+ *     cliques of G+(u) that contain it, and by the plain definition.
  *
  * Colour hash (the paper leaves the colouring's randomness unspecified; this is
  * the reading used): SplitMix64's finaliser mix64 (Steele, Lea & Flood 2014),
@@ -516,4 +519,102 @@ int kco_work_per_root(const kco_graph *g, int k, int threads, uint64_t *inter, u
     }
     (void)threads;
     return status;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Per-node clique-membership counts.
+ *
+ * Section 3 notes that the round-3 reducer of root u can also report, for each
+ * node v, how many of the cliques it finds contain v, and that summing these
+ * reports over all sub-problems G+(u) gives the number of k-cliques that contain
+ * v.  kco_count_per_node follows that route: every (k-1)-clique of G+(u) is listed
+ * explicitly (the same intersection recursion as cnt, with the chosen nodes kept
+ * on a path) and adds one to u and to each of its own nodes.
+ *
+ * kco_count_node is the plain definition instead: the k-cliques that contain v
+ * are the (k-1)-cliques inside the neighbourhood Gamma(v); Gamma(v) is sorted by
+ * the order and counted with cnt (each clique once, by its smallest node). */
+static int add_checked(uint64_t *c, uint64_t x) {
+    uint64_t old;
+    #pragma omp atomic capture
+    { old = *c; *c += x; }
+    return old + x < old ? KCO_EOVERFLOW : KCO_OK;
+}
+
+/* List the l-cliques inside P (sorted by the order); each adds one to the nodes on
+ * the path (depth entries) and to its own. */
+static int list_attr(const kco_graph *g, const uint32_t *P, uint64_t np, int l, uint32_t *buf, uint32_t *path,
+                     int depth, uint64_t *counts) {
+    if (l <= 0) {
+        for (int t = 0; t < depth; ++t) {
+            int st = add_checked(&counts[path[t]], 1);
+            if (st) return st;
+        }
+        return KCO_OK;
+    }
+    for (uint64_t i = 0; i < np; ++i) {
+        path[depth] = P[i];
+        uint64_t nq = intersect(g, P, np, P[i], buf);
+        int st = list_attr(g, buf, nq, l - 1, buf + np, path, depth + 1, counts);
+        if (st) return st;
+    }
+    return KCO_OK;
+}
+
+int kco_count_per_node(const kco_graph *g, int k, int threads, uint64_t *counts) {
+    if (!g || !counts || k < 1) return KCO_EINVAL;
+    memset(counts, 0, sizeof(uint64_t) * g->n);
+    int status = KCO_OK;
+#ifdef _OPENMP
+    if (threads <= 0) threads = omp_get_max_threads();
+    #pragma omp parallel for schedule(dynamic, 16) num_threads(threads)
+#endif
+    for (int64_t x = 0; x < (int64_t)g->n; ++x) {
+        uint32_t u = (uint32_t)x;
+        uint64_t d = g->hp[u + 1] - g->hp[u];
+        uint32_t *buf = (uint32_t *)malloc(sizeof(uint32_t) * ((uint64_t)k * d + 1));
+        uint32_t *path = (uint32_t *)malloc(sizeof(uint32_t) * ((uint64_t)k + 1));
+        int st = (!buf || !path) ? KCO_ENOMEM : KCO_OK;
+        if (st == KCO_OK) {
+            path[0] = u;  /* the root belongs to every clique of its sub-problem */
+            st = list_attr(g, g->hn + g->hp[u], d, k - 1, buf, path, 1, counts);
+        }
+        free(buf);
+        free(path);
+        if (st) {
+            #pragma omp critical
+            status = st;
+        }
+    }
+    (void)threads;
+    return status;
+}
+
+static const kco_graph *sort_graph;  /* qsort has no context argument */
+static int cmp_by_order(const void *a, const void *b) {
+    uint64_t x = key_of(sort_graph, *(const uint32_t *)a), y = key_of(sort_graph, *(const uint32_t *)b);
+    return (x > y) - (x < y);
+}
+
+int kco_count_node(const kco_graph *g, uint32_t v, int k, uint64_t *out) {
+    if (!g || !out || v >= g->n || k < 1) return KCO_EINVAL;
+    uint64_t dv = g->deg[v];
+    uint32_t *nb = (uint32_t *)malloc(sizeof(uint32_t) * (dv + 1));
+    uint32_t *buf = (uint32_t *)malloc(sizeof(uint32_t) * ((uint64_t)k * dv + 1));
+    if (!nb || !buf) { free(nb); free(buf); return KCO_ENOMEM; }
+    uint64_t c = 0;
+    for (uint64_t i = 0; i < g->m; ++i) {
+        if (g->eu[i] == v) nb[c++] = g->ev[i];
+        else if (g->ev[i] == v) nb[c++] = g->eu[i];
+    }
+    int st = KCO_OK;
+    #pragma omp critical(kco_sort)
+    {
+        sort_graph = g;
+        qsort(nb, c, sizeof(uint32_t), cmp_by_order);
+    }
+    st = cnt(g, nb, c, k - 1, buf, out);
+    free(nb);
+    free(buf);
+    return st;
 }

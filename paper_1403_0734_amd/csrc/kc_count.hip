@@ -35,38 +35,7 @@ constexpr int WG = 256;  // threads per block in every count kernel
 constexpr int WAVES = WG / 64;
 
 // ----------------------------------------------------------------------------
-// small device helpers
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// position of the r-th set bit (r from 0) of w; w must have more than r bits set
-__device__ __forceinline__ uint32_t select_bit(uint64_t w, uint32_t r) {
-    uint32_t pos = 0;
-#pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) {
-        const uint32_t c = (uint32_t)__popcll(w & ((1ull << s) - 1ull));
-        if (r >= c) {
-            r -= c;
-            w >>= s;
-            pos += s;
-        }
-    }
-    return pos;
-}
-
-// largest i in [0, d) with seg[i] <= e  (seg[0] = 0 <= e)
-__device__ __forceinline__ uint32_t seg_find(const uint32_t *seg, uint32_t d, uint32_t e) {
-    uint32_t lo = 0, hi = d;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (seg[mid] <= e) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
+// small device helpers (wave sync, bit select, segment search: kc_internal.h)
 // first j in [0, d) with nb[j] >= y, or d
 __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *nb, uint32_t d, uint32_t y) {
     uint32_t lo = 0, hi = d;
@@ -339,7 +308,7 @@ __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int el
     } else {
         A.epre[lane] = ei - ce;
     }
-    wave_sync();
+    kc_wave_sync();
     if (R <= 2 || (R == 3 && (listed || SPREAD3))) {
         // Up to three levels below an edge: lane l takes edges l, l + 64, ...  An
         // edge task (i, j) adds the (R+1)-cliques of the candidate set
@@ -368,7 +337,7 @@ __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int el
                 }
                 r0 = (uint32_t)__builtin_amdgcn_readlane((int)i, 63);
                 const uint64_t ri = A.rows[i];
-                P = t < E ? ri & A.rows[select_bit(ri, t - A.epre[i])] : 0ull;
+                P = t < E ? ri & A.rows[kc_select_bit(ri, t - A.epre[i])] : 0ull;
             }
             if (R == 1) {
                 acc += (uint64_t)__popcll(P);
@@ -394,7 +363,7 @@ __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int el
                 }
             }
         }
-        wave_sync();
+        kc_wave_sync();
         return;
     }
     // Idle lanes are refilled together, once at least REFILL of them wait (or
@@ -426,9 +395,9 @@ __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int el
                     const uint32_t e = A.elist[t];
                     P = A.rows[e >> 8] & A.rows[e & 255u];
                 } else {
-                    const uint32_t i = seg_find(A.epre, s, t);
+                    const uint32_t i = kc_seg_find(A.epre, s, t);
                     const uint64_t ri = A.rows[i];
-                    P = ri & A.rows[select_bit(ri, t - A.epre[i])];
+                    P = ri & A.rows[kc_select_bit(ri, t - A.epre[i])];
                 }
                 if (R == 1) {
                     acc += (uint64_t)__popcll(P);
@@ -462,7 +431,7 @@ __device__ __forceinline__ void local_count(LocalArea<NS> &A, uint32_t s, int el
             }
         }
     }
-    wave_sync();
+    kc_wave_sync();
 }
 
 // ============================================================================
@@ -480,7 +449,7 @@ struct LocalArea2 {
 
 __device__ __forceinline__ uint32_t select_bit2(uint64_t w0, uint64_t w1, uint32_t r) {
     const uint32_t c0 = (uint32_t)__popcll(w0);
-    return r < c0 ? select_bit(w0, r) : 64u + select_bit(w1, r - c0);
+    return r < c0 ? kc_select_bit(w0, r) : 64u + kc_select_bit(w1, r - c0);
 }
 
 // (fpart, fparts): the first-node filter of local_count.
@@ -506,7 +475,7 @@ __device__ __forceinline__ void local_count2(LocalArea2<NS> &A, uint32_t s, int 
     const uint32_t sa = incl - ca - cb, sb = incl - cb;  // first edges of rows 2*lane, 2*lane+1
     A.epre[2 * lane] = sa;
     A.epre[2 * lane + 1] = sb;
-    wave_sync();
+    kc_wave_sync();
     if (R <= 2) {
         // as in local_count: lane l takes edges l, l + 64, ..., each edge's row
         // found from the row starts that fall in its batch of 64 edges
@@ -543,7 +512,7 @@ __device__ __forceinline__ void local_count2(LocalArea2<NS> &A, uint32_t s, int 
                 acc += (uint64_t)(__popcll(p0 & A.rows[v][0]) + __popcll(p1 & A.rows[v][1]));
             }
         }
-        wave_sync();
+        kc_wave_sync();
         return;
     }
     constexpr uint32_t REFILL = 16;
@@ -578,7 +547,7 @@ __device__ __forceinline__ void local_count2(LocalArea2<NS> &A, uint32_t s, int 
             const uint32_t t = next + (uint32_t)__popcll(idle & kc_lanemask_lt());
             next += nidle;
             if (depth < 0 && t < E) {
-                const uint32_t i = seg_find(A.epre, s, t);
+                const uint32_t i = kc_seg_find(A.epre, s, t);
                 const uint64_t r0 = A.rows[i][0], r1 = A.rows[i][1];
                 const uint32_t j = select_bit2(r0, r1, t - A.epre[i]);
                 const uint64_t p0 = r0 & A.rows[j][0], p1 = r1 & A.rows[j][1];
@@ -620,7 +589,7 @@ __device__ __forceinline__ void local_count2(LocalArea2<NS> &A, uint32_t s, int 
             }
         }
     }
-    wave_sync();
+    kc_wave_sync();
 }
 
 // ============================================================================
@@ -652,10 +621,19 @@ struct WaveStage {
 static_assert(offsetof(WaveStage, rows) == 0 && offsetof(LocalArea<1>, rows) == 0,
               "staging rows must alias the local graph's rows");
 
+// The one-wave tier counts in place from k = 8 on.  At k = 7 the in-place kernel's
+// extra registers and smaller local areas let more one-wave blocks share the CUs
+// with the workgroup tier that runs beside it, and the workgroup tier, which takes
+// longer, slows by more than the one-wave tier gains.
+constexpr bool wave_inplace(int k) { return k >= 8; }
+constexpr int wave_stack(int k) {
+    return wave_inplace(k) ? (k - 5 > 1 ? k - 5 : 1) : (k - 4 > 1 ? k - 4 : 1);
+}
+
 template <int K>
 struct WaveSmem {
     union {
-        LocalArea<(K > 5 ? K - 5 : 1)> A;
+        LocalArea<wave_stack(K)> A;
         WaveStage S;
     };
     uint32_t nb[64];      // the packed Gamma+ lists
@@ -733,9 +711,9 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
         if (single || g == 0) g = 1;
         const uint32_t S = __shfl(incl, ci + g - 1, 64) - before;  // lanes used
         if (lane >= ci && lane < ci + g) sm.rstart[lane - ci] = incl - dl - before;
-        wave_sync();
+        kc_wave_sync();
         uint32_t r = 0;  // packed root of this lane
-        if (lane < S) r = seg_find(sm.rstart, g, lane);
+        if (lane < S) r = kc_seg_find(sm.rstart, g, lane);
         const uint32_t rl = ci + r;
         const uint32_t u = __shfl(my_u, rl, 64);
         const uint64_t rbase = __shfl(my_base, rl, 64);
@@ -759,7 +737,7 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
                 } else {
                     const uint32_t mc = mine ? root_colour(p.seed, p.rank2id[u], p.rank2id[a], p.c) : 0u;
                     sm.colr[lane] = mc;
-                    wave_sync();
+                    kc_wave_sync();
                     uint64_t x = row, kept = 0;
                     while (x) {
                         const uint32_t j = (uint32_t)__builtin_ctzll(x);
@@ -779,9 +757,9 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
                 const uint64_t bal = __ballot(keep);
                 const uint32_t idx = (uint32_t)__popcll(bal & kc_lanemask_lt());
                 sm.nb[lane] = 0xFFFFFFFFu;
-                wave_sync();
+                kc_wave_sync();
                 if (keep) sm.nb[idx] = a;
-                wave_sync();
+                kc_wave_sync();
                 d = (uint32_t)__popcll(bal);
                 a = sm.nb[lane];
             }
@@ -824,12 +802,12 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
             for (uint32_t h = 0; h < STAGE_WINDOWS; ++h) sm.S.flag[64 * h + lane] = 0;
             const bool percol = p.colored && p.scheme == KC_COLOR_PER_ROOT;
             if (percol) sm.colr[lane] = lane < d ? root_colour(p.seed, p.rank2id[u], p.rank2id[a], p.c) : 0u;
-            wave_sync();
+            kc_wave_sync();
             if (lane < d) {
                 const uint32_t h = filt_hash(a);
                 atomicOr(&sm.S.filt[h >> 5], 1u << (h & 31u));
             }
-            wave_sync();
+            kc_wave_sync();
 
             // staging: row i bit j = [a_j in Gamma+(a_i)], j inside i's block.  The
             // flattened out-lists are read 64 elements per step; the list of each
@@ -841,7 +819,7 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
             const uint64_t le_mask = kc_lanemask_lt() | (1ull << lane);
             for (uint32_t w0 = 0; w0 < Ttot; w0 += 64u * STAGE_WINDOWS) {
                 if (len && excl >= w0 && excl - w0 < 64u * STAGE_WINDOWS) sm.S.flag[excl - w0] = (uint8_t)(lane + 1u);
-                wave_sync();
+                kc_wave_sync();
                 uint32_t iw[STAGE_WINDOWS], yw[STAGE_WINDOWS];
 #pragma unroll
                 for (uint32_t h = 0; h < STAGE_WINDOWS; ++h) {
@@ -873,31 +851,31 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
                     }
                     qt += (uint32_t)__popcll(kb);
                     if (qt - qh >= 64u) {
-                        wave_sync();
+                        kc_wave_sync();
                         wave_stage_check(sm, qh, 64u, percol);
                         qh += 64u;
-                        wave_sync();
+                        kc_wave_sync();
                     }
                 }
             }
             if (qt != qh) {
-                wave_sync();
+                kc_wave_sync();
                 wave_stage_check(sm, qh, qt - qh, percol);
             }
         }
         if (MODE == MODE_STORE) {
             // keep the staged rows (root-local bit positions) for later counts
-            wave_sync();
+            kc_wave_sync();
             if (lane < d) {
                 const uint64_t row = sm.A.rows[lane] >> r0;
                 p.lrows[rbase + (lane - r0)] = row;
                 acc += (uint64_t)__popcll(row);  // the root's triangles (q_3), for free
             }
-            wave_sync();
+            kc_wave_sync();
             continue;
         }
-        wave_sync();
-        local_count<LC_REG_WAVE, true, true>(sm.A, d, K - 1, acc);
+        kc_wave_sync();
+        local_count<LC_REG_WAVE, true, wave_inplace(K)>(sm.A, d, K - 1, acc);
 
         if (p.per_root) {
             const uint64_t q = kc_wave_sum_checked(acc, &ovf);
@@ -909,7 +887,7 @@ __global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
                 wave_total = nt;
             }
         }
-        wave_sync();
+        kc_wave_sync();
     }
     // per-lane sums of many roots: one exact, carry-checked reduction at the end
     const uint64_t rest = kc_wave_sum_checked(acc, &ovf);
@@ -1013,7 +991,7 @@ __device__ __forceinline__ uint32_t compact_local(const uint64_t *P, uint32_t lo
         if ((word >> lane) & 1ull) A.members[nmem + (uint32_t)__popcll(word & kc_lanemask_lt())] = 64 * l + lane;
         nmem += (uint32_t)__popcll(word);
     }
-    wave_sync();
+    kc_wave_sync();
     uint64_t lrow = 0;
     if (lane < nmem) {
         const uint32_t v = A.members[lane];
@@ -1034,7 +1012,7 @@ __device__ __forceinline__ uint32_t compact_local(const uint64_t *P, uint32_t lo
         }
     }
     A.rows[lane] = lrow;
-    wave_sync();
+    kc_wave_sync();
     return nmem;
 }
 
@@ -1049,7 +1027,7 @@ __device__ __forceinline__ uint32_t compact_local2(const uint64_t *P, uint32_t l
         if ((word >> lane) & 1ull) A.members[nmem + (uint32_t)__popcll(word & kc_lanemask_lt())] = 64 * l + lane;
         nmem += (uint32_t)__popcll(word);
     }
-    wave_sync();
+    kc_wave_sync();
     for (uint32_t half = 0; half < 2; ++half) {
         const uint32_t t = lane + 64 * half;
         uint64_t l0 = 0, l1 = 0;
@@ -1076,7 +1054,7 @@ __device__ __forceinline__ uint32_t compact_local2(const uint64_t *P, uint32_t l
         A.rows[t][0] = l0;
         A.rows[t][1] = l1;
     }
-    wave_sync();
+    kc_wave_sync();
     return nmem;
 }
 
@@ -1088,13 +1066,13 @@ __device__ __forceinline__ void wide_edges(const uint64_t *C, uint32_t lo, uint3
                                            uint32_t *mem, uint64_t &acc, uint32_t fpart = 0, uint32_t fparts = 1) {
     const uint32_t lane = kc_lane();
     auto flush = [&](uint32_t k) {
-        wave_sync();
+        kc_wave_sync();
         if (lane < k) {
             const uint32_t v = mem[lane];
             const uint64_t *rv = bm_row(bm, v, W);
             for (uint32_t l = (v + 1) >> 6; l < W; ++l) acc += (uint64_t)__popcll(rv[l] & C[l]);
         }
-        wave_sync();
+        kc_wave_sync();
     };
     uint32_t cnt = 0;
     uint64_t cls = ~0ull;  // members of the filter's class in this word
@@ -1324,7 +1302,7 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                     }
                 } else {
                     for (uint32_t e = tid; e < Ttot; e += WGT) {
-                        const uint32_t i = seg_find(seg, d, e);
+                        const uint32_t i = kc_seg_find(seg, d, e);
                         const uint32_t y = p.ocol[delta[i] + e];
                         if (y > alast) continue;
                         const uint32_t j = hash_find(htab, hbits, nb, y);
@@ -1401,7 +1379,7 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                 uint32_t lo[KC_KMAX];
                 lo[0] = lo0;
                 int depth = 0;
-                wave_sync();
+                kc_wave_sync();
                 while (depth >= 0) {
                     uint64_t *cur = stk + (size_t)depth * Wc;
                     const int need = (K - 2) - depth;
@@ -1428,7 +1406,7 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                             break;
                         }
                     }
-                    wave_sync();
+                    kc_wave_sync();
                     if (v < 0) {
                         --depth;
                         continue;
@@ -1444,11 +1422,11 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                         cpc += (uint32_t)__popcll(x);
                     }
                     cpc = kc_wave_sum_u32(cpc);
-                    wave_sync();
+                    kc_wave_sync();
                     if ((int)cpc < cn) continue;
                     if (cn == 2) {
                         wide_edges(nxt, clo, W, bm, A.members, acc);
-                        wave_sync();
+                        kc_wave_sync();
                     } else if (cpc <= 64) {
                         const uint32_t sN = compact_local(nxt, clo, W, bm, W, A);
                         local_count<LC_REG_WG, false, false>(A, sN, cn, acc);
@@ -1527,7 +1505,7 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                             rs[r] = (uint8_t)(incl - v);
                             rt[r] = (uint8_t)lane;
                         }
-                        wave_sync();
+                        kc_wave_sync();
                         uint64_t lrow = 0;
                         if (lane < S) {
                             uint32_t r = 0, hi = g;  // last block starting at or before this lane
@@ -1548,7 +1526,7 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                                 rem -= c;
                                 w = ri[++l];
                             }
-                            const uint32_t vn = 64 * l + select_bit(w, rem);
+                            const uint32_t vn = 64 * l + kc_select_bit(w, rem);
                             // its row inside row i, renumbered by rank in row i
                             const uint64_t *rv = bm_row(bm, vn, W);
                             const uint32_t vlo = (vn + 1) >> 6;
@@ -1572,10 +1550,10 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                         }
                         if (K > 4) {
                             A.rows[lane] = lrow;
-                            wave_sync();
+                            kc_wave_sync();
                             local_count<LC_REG_WG, false, false>(A, S, K - 2, acc);
                         } else {
-                            wave_sync();  // rs/rt are rewritten by the next pack
+                            kc_wave_sync();  // rs/rt are rewritten by the next pack
                         }
                         cm &= ~fit;
                     }

@@ -184,6 +184,9 @@ kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_a
                           size_t slice_words, uint32_t scratch_blocks, hipStream_t s,
                           hipEvent_t *tier_ev = nullptr, bool use_side = false);
 
+// Stage every root's G+(u) into the handle's cache (one-wave tier split at wd); the
+// handle is left uncached (staged = -1) when the cache would not fit.
+kc_status kc_stage(kc_graph *g, int wd);
 // Stage the G+(u) of the roots in queue q of graph g into caches allocated here
 // (rows for roots with out-degree <= wd, packed bitmaps above), enqueued on g's
 // stream with a result block the caller owns (KC_RES_WORDS words); cached is false
@@ -276,6 +279,38 @@ __host__ __device__ inline double kc_learned_logwork(uint32_t prio) { return (do
 
 KC_DEV uint32_t kc_lane() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 KC_DEV uint64_t kc_lanemask_lt() { return (1ull << kc_lane()) - 1ull; }
+
+// LDS writes of a wave made visible to the wave's other lanes
+KC_DEV void kc_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// position of the r-th set bit (r from 0) of w; w must have more than r bits set
+KC_DEV uint32_t kc_select_bit(uint64_t w, uint32_t r) {
+    uint32_t pos = 0;
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        const uint32_t c = (uint32_t)__popcll(w & ((1ull << s) - 1ull));
+        if (r >= c) {
+            r -= c;
+            w >>= s;
+            pos += s;
+        }
+    }
+    return pos;
+}
+
+// largest i in [0, d) with seg[i] <= e  (seg[0] = 0 <= e)
+KC_DEV uint32_t kc_seg_find(const uint32_t *seg, uint32_t d, uint32_t e) {
+    uint32_t lo = 0, hi = d;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (seg[mid] <= e) lo = mid; else hi = mid;
+    }
+    return lo;
+}
 
 // SplitMix64 finaliser (Steele, Lea & Flood 2014)
 __host__ __device__ inline uint64_t kc_mix64(uint64_t z) {

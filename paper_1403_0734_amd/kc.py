@@ -25,7 +25,7 @@ EXPORTS = [
     "kc_count_batch", "kc_set_schedule", "kc_train_schedule", "kc_graph_info", "kc_get_csr",
     "kc_get_oriented", "kc_last_timings", "kc_graph_destroy", "kc_status_str",
     "kc_set_tuning", "kc_get_tuning", "kc_autotune", "kc_last_tier_timings", "kc_count_noalloc",
-    "kc_predict_work", "kc_mlp_step", "kc_last_stage_timings",
+    "kc_predict_work", "kc_mlp_step", "kc_last_stage_timings", "kc_count_per_node",
 ]
 
 
@@ -65,6 +65,7 @@ def load(path: str = LIB_PATH):
         "kc_count_colored": (i32, [P, i32, u32, u64, i32, ctypes.POINTER(kc_estimate)]),
         "kc_count_pair_sampled": (i32, [P, i32, ctypes.c_double, u64, ctypes.POINTER(kc_estimate)]),
         "kc_count_per_root": (i32, [P, i32, P, P]),
+        "kc_count_per_node": (i32, [P, i32, P]),
         "kc_count_noalloc": (i32, [P, i32, P]),
         "kc_predict_work": (i32, [P, i32, P, P]),
         "kc_mlp_step": (i32, [P, P, P, i32, ctypes.c_float, P, P, u32, P, ctypes.POINTER(ctypes.c_float), P]),
@@ -144,6 +145,11 @@ def kc_count_pair_sampled(g: int, k: int, p: float, seed: int) -> kc_estimate:
 
 def kc_count_per_root(g: int, k: int, dev_counts, dev_work=None):
     check(load().kc_count_per_root(g, k, _ptr(dev_counts), _ptr(dev_work)), "kc_count_per_root")
+
+
+def kc_count_per_node(g: int, k: int, dev_counts):
+    """Per-node clique-membership counts into device uint64[n] (by original id)."""
+    check(load().kc_count_per_node(g, k, _ptr(dev_counts)), "kc_count_per_node")
 
 
 def kc_count_noalloc(g: int, k: int, dev_out):

@@ -406,3 +406,64 @@ def test_work_wide_root_words():
     inter, words = g.work_root(u, 3)
     assert inter == d
     assert words == sum(((d - 1) // 64 - (i + 1) // 64 + 1) for i in range(d - 1))
+
+
+# ------------------------------------------------- per-node membership counts
+# Section 3 (remark after the round-3 reducers): summing each sub-problem's
+# per-node report over all roots gives the k-cliques that contain each node.
+
+@pytest.mark.parametrize("n", [1, 2, 5, 9, 14])
+def test_per_node_complete_graph(n):
+    g = og(S.complete(n))
+    for k in range(1, min(n, 7) + 1):
+        np.testing.assert_array_equal(g.count_per_node(k), np.full(n, math.comb(n - 1, k - 1), np.uint64))
+
+
+@pytest.mark.parametrize("parts", [[1, 2, 3, 4, 2], [5, 5, 5], [3, 1, 4, 1, 5, 9, 2]])
+def test_per_node_multipartite_closed_form(parts):
+    # a node of block b lies in the k-cliques that take one node from each of k - 1
+    # other blocks: e_{k-1} of the other blocks' sizes
+    g = og(S.complete_multipartite(parts))
+    block = [b for b, s in enumerate(parts) for _ in range(s)]
+    for k in range(1, len(parts) + 2):
+        want = [elementary_symmetric(parts[:b] + parts[b + 1:], k - 1) for b in block]
+        np.testing.assert_array_equal(g.count_per_node(k), np.array(want, np.uint64))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_per_node_bruteforce(seed):
+    n = 9 + seed
+    el = S.random_graph(n, 0.55, 300 + seed, dup_frac=0.1, loops=2)
+    g = og(el)
+    for k in range(1, 7):
+        cl, _ = brute_cliques(n, edge_set(el), k)
+        want = np.zeros(n, np.uint64)
+        for c in cl:
+            for v in c:
+                want[v] += 1
+        np.testing.assert_array_equal(g.count_per_node(k), want, err_msg=f"k={k}")
+
+
+@pytest.mark.parametrize("el", [S.random_graph(120, 0.15, 5), S.turan(40, 6),
+                                S.planted_small(150, 0.03, [list(range(0, 12)), list(range(40, 49))], 7),
+                                S.hub_bipartite(5, 80, 0.2, 3)], ids=lambda e: e.name)
+def test_per_node_sums_and_definition(el):
+    g = og(el)
+    deg = g.degrees()
+    for k in range(1, 7):
+        c = g.count_per_node(k)
+        # every k-clique has k nodes
+        assert int(c.sum()) == k * g.count(k), k
+        if k == 2:
+            np.testing.assert_array_equal(c, deg.astype(np.uint64))
+        # the route through the sub-problems agrees with the plain definition
+        for v in range(0, el.n, max(1, el.n // 17)):
+            assert int(c[v]) == g.count_node(v, k), (k, v)
+
+
+def test_per_node_disjoint_union():
+    a, b = S.complete(6), S.turan(12, 3)
+    g = og(S.disjoint_union(a, b))
+    c = g.count_per_node(3)
+    np.testing.assert_array_equal(c[:6], og(a).count_per_node(3))
+    np.testing.assert_array_equal(c[6:], og(b).count_per_node(3))
