@@ -51,7 +51,13 @@ def bounded_ks(og, lo=1, hi=K.KC_KMAX, budget=2e7):
 MULTI_TILE = [G.chung_lu(50000, 2.1, 20.0, 1500.0, 5), S.random_graph(3000, 0.05, 6, dup_frac=0.2, loops=30)]
 
 
-@pytest.mark.parametrize("el", SMALL + MULTI_TILE, ids=lambda e: e.name[:40])
+# a hub of degree 19999 with the smallest id (every edge keyed by it) and with the
+# largest (every edge keyed by a leaf)
+HUBS = [S.disjoint_union(S.star(20000), S.random_graph(200, 0.1, 9)),
+        S.relabel(S.star(20000), np.arange(20000)[::-1].copy())]
+
+
+@pytest.mark.parametrize("el", SMALL + MULTI_TILE + HUBS, ids=lambda e: e.name[:40])
 def test_csr_and_orientation_match_oracle(el):
     announce(f"csr/orientation {el.name}")
     og = O.OracleGraph.from_edgelist(el)
