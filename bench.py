@@ -39,7 +39,7 @@ WORKLOADS = {
     "rmat22": ("workload_rmat22", [3, 4, 5]),
     "er2000": ("workload_er2000", [3, 4]),
 }
-EXTRAS = ["peaks", "chung_lu_1m", "batch", "schedule", "rmat22"]
+EXTRAS = ["peaks", "chung_lu_1m", "per_node", "batch", "schedule", "rmat22"]
 
 
 def log(msg):
@@ -190,6 +190,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(el, ks, qs)
     if "chung_lu_1m" in extras and args.workload != "chung_lu_1m":
         out["chung_lu_1m"] = bench_secondary(K, torch, np, G, stream, "chung_lu_1m")
+    if "per_node" in extras:
+        out["per_node"] = bench_per_node(K, torch, np, el, src, dst, stream, ks, qs)
     if "batch" in extras and args.batch_graphs > 0:
         out["batch"] = bench_batch(args, K, torch, stream)
         K.kc_set_tuning(defaults=True)  # the batch's tuning does not carry over
@@ -404,6 +406,39 @@ def bench_secondary(K, torch, np, G, stream, name, steps=5):
     dt = (time.perf_counter() - t0) / steps
     return {"workload": el.name, "ks": ks, "q": {str(k): v for k, v in qs.items()}, "ms_per_step": dt * 1e3,
             "kcliques_per_s": sum(qs.values()) / dt}
+
+
+def bench_per_node(K, torch, np, el, src, dst, stream, ks, qs, reps=3):
+    """Per-node clique-membership counts (kc_count_per_node) on the headline graph at
+    every k, beside the total count on the same staged handle: median of reps timed
+    calls after one untimed call each; the counts must sum to k * q_k."""
+    h = K.kc_graph_create(src.data_ptr(), dst.data_ptr(), el.m_in, el.n, True, stream)
+    out = {}
+    try:
+        K.kc_orient(h)
+        c = torch.zeros(el.n, dtype=torch.int64, device="cuda:0")
+        for k in ks:
+            K.kc_count(h, k)
+            K.kc_count_per_node(h, k, c.data_ptr())
+            tc, tp = [], []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                q = K.kc_count(h, k)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                K.kc_count_per_node(h, k, c.data_ptr())
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                tc.append((t1 - t0) * 1e3)
+                tp.append((t2 - t1) * 1e3)
+            total = int(c.cpu().numpy().view(np.uint64).sum(dtype=np.uint64))
+            out[str(k)] = {"ms_per_node": round(median(tp), 3), "ms_count": round(median(tc), 3),
+                           "ratio": round(median(tp) / median(tc), 2), "sum_is_k_q": total == k * qs[k]}
+            log(f"per-node k={k}: {out[str(k)]}")
+    finally:
+        K.kc_graph_destroy(h)
+    return out
 
 
 def bench_batch(args, K, torch, stream):
