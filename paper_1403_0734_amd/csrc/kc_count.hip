@@ -939,32 +939,48 @@ __host__ __device__ inline size_t wg_local_bytes(int K) {
 __host__ __device__ inline size_t wg_static_lds(int K, int nw = WAVES) { return wg_local_bytes(K) * nw + 128; }
 
 // Layout of one workgroup's arena (LDS, or a global slice for the scratch tier)
-// for out-degree cap D, clique size K and nw waves per block.
+// for out-degree cap D, clique size K and nw waves per block.  A count from the
+// staged cache needs only the wide stacks and the bitmap, plus the out-list and
+// colour arrays when it applies a colouring (lean = 1: cached, uncoloured; 2: cached,
+// coloured; 0: staging).  Fields a layout leaves out point at offset 0 and are not
+// read.
 struct WgLayout {
     size_t nb, seg, colr, delta, stk, htab, bm, bytes;
     uint32_t W, hbits;
 };
-__host__ __device__ inline WgLayout wg_layout(uint32_t D, int K, int nw = WAVES) {
+__host__ __device__ inline WgLayout wg_layout(uint32_t D, int K, int nw = WAVES, int lean = 0) {
     WgLayout L;
     const uint32_t W = (D + 63) / 64;
     const int levels = K > 3 ? K - 3 : 1;  // wide depth-first stack entries
     L.W = W;
-    size_t o = 0;
-    L.nb = o;    o += (size_t)D * 4;
-    L.seg = o;   o += ((size_t)D + 1) * 4;
-    L.colr = o;  o += (size_t)D * 4;
-    o = (o + 3) & ~(size_t)3;
     L.hbits = hash_bits(D);
-    // the table lives in the per-wave local-graph areas (idle while staging) when it fits
-    const size_t hbytes = ((size_t)1 << L.hbits) * 2;
-    L.htab = hbytes <= wg_local_bytes(K) * nw ? (size_t)-1 : o;
-    if (L.htab != (size_t)-1) o += hbytes;
+    size_t o = 0;
+    L.nb = L.seg = L.colr = L.delta = 0;
+    L.htab = (size_t)-1;
+    if (lean != 1) {
+        L.nb = o;    o += (size_t)D * 4;
+        L.seg = o;   o += ((size_t)D + 1) * 4;
+        L.colr = o;  o += (size_t)D * 4;
+        o = (o + 3) & ~(size_t)3;
+    }
+    if (lean == 0) {
+        // the table lives in the per-wave local-graph areas (idle while staging) when it fits
+        const size_t hbytes = ((size_t)1 << L.hbits) * 2;
+        L.htab = hbytes <= wg_local_bytes(K) * nw ? (size_t)-1 : o;
+        if (L.htab != (size_t)-1) o += hbytes;
+        o = (o + 7) & ~(size_t)7;
+        L.delta = o; o += (size_t)D * 8;
+    }
     o = (o + 7) & ~(size_t)7;
-    L.delta = o; o += (size_t)D * 8;
     L.stk = o;   o += (size_t)nw * levels * W * 8;
     L.bm = o;    o += tri_words(D) * 8;
     L.bytes = o;
     return L;
+}
+
+// the layout a launch of the given mode uses
+__host__ __device__ inline int wg_lean(int mode, bool colored) {
+    return mode == MODE_CACHED ? (colored ? 2 : 1) : 0;
 }
 
 __device__ __forceinline__ const uint64_t *bm_row(const uint64_t *bm, uint32_t i, uint32_t W) {
@@ -1108,7 +1124,7 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
     __shared__ uint64_t s_red[NW];
     __shared__ int s_ovf[NW];
     unsigned char *arena = GLOBAL ? (unsigned char *)(p.gscratch + (size_t)blockIdx.x * p.slice_words) : smem_dyn;
-    const WgLayout L = wg_layout(p.dcap, K, NW);
+    const WgLayout L = wg_layout(p.dcap, K, NW, wg_lean(MODE, p.colored));
     uint32_t *nb = (uint32_t *)(arena + L.nb);
     uint32_t *seg = (uint32_t *)(arena + L.seg);
     uint32_t *colr = (uint32_t *)(arena + L.colr);
@@ -1729,7 +1745,7 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
             for (int i = 0; i < 3; ++i) {
                 const int nw = nws[i];
                 if (tu.wg_waves && tu.wg_waves != nw) continue;
-                const WgLayout L = wg_layout(dmax < 65 ? 65 : dmax, K, nw);
+                const WgLayout L = wg_layout(dmax < 65 ? 65 : dmax, K, nw, wg_lean(MODE, base.colored));
                 const size_t per_block = L.bytes + stat[i] + 256;
                 if (per_block > di.lds_max) continue;
                 uint32_t per_cu = (uint32_t)(di.lds_max / per_block);
@@ -1760,7 +1776,7 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
             p.dcap = dmax < 65 ? 65 : dmax;
             const Shape sh = shape(dmax);
             const int nw = nws[sh.idx];
-            const WgLayout L = wg_layout(p.dcap, K, nw);
+            const WgLayout L = wg_layout(p.dcap, K, nw, wg_lean(MODE, p.colored));
             uint32_t blocks = (uint32_t)di.cus * sh.per_cu;
             if (blocks > count) blocks = count;
             const bool l2 = items && q.wg_l2;
