@@ -103,9 +103,9 @@ def planted_small(n: int, p: float, cliques, seed: int) -> EdgeList:
 
 def hub_bipartite(na: int, nb: int, p: float, seed: int) -> EdgeList:
     """Every node of A = [0, na) joined to every node of B = [na, na + nb), plus
-    G(nb, p) inside B (numpy PCG64 stream).  With nb > na, B's nodes have the larger
-    degrees, so every node of A keeps (almost) all of B as its high neighbours:
-    high-neighbourhoods of about nb nodes on a sparse graph."""
+    G(nb, p) inside B (numpy PCG64 stream).  A node of A has degree nb, one of B about
+    na + p (nb - 1); when that is larger (na > nb (1 - p) roughly), every node of A
+    keeps all of B as its high neighbours: high-neighbourhoods of nb nodes."""
     rng = np.random.default_rng(seed)
     a = np.repeat(np.arange(na, dtype=np.uint64), nb)
     b = np.tile(np.arange(na, na + nb, dtype=np.uint64), na)

@@ -101,7 +101,7 @@ void kc_graph_destroy(kc_graph *g) {
     if (!g) return;
     kc_batch_forget(g->serial);
     void *bufs[] = {g->rowptr, g->col,  g->deg, g->ukeys, g->optr,  g->ocol,  g->rank2id, g->id2rank,
-                    g->mlp,    g->d_res, g->dq,  g->tri,   g->lrows, g->wbits, g->woff, g->feat, g->wq, g->wedges};
+                    g->mlp,    g->d_res, g->dq,  g->tri,   g->lrows, g->wbits, g->woff, g->feat, g->wq, g->wedges, g->wq2};
     for (void *b : bufs)
         kc_cache_free(b, g->stream);
     for (auto &L : g->lq) {
@@ -117,6 +117,9 @@ void kc_graph_destroy(kc_graph *g) {
     if (g->fork) (void)hipEventDestroy(g->fork);
     if (g->join) (void)hipEventDestroy(g->join);
     if (g->side) (void)hipStreamDestroy(g->side);
+    if (g->fork2) (void)hipEventDestroy(g->fork2);
+    if (g->join2) (void)hipEventDestroy(g->join2);
+    if (g->side2) (void)hipStreamDestroy(g->side2);
     delete g;
 }
 

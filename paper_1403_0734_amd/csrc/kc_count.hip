@@ -1645,7 +1645,8 @@ DevInfo dev_info(int device) {
 template <int K, int MODE>
 void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors, const DevInfo &di, hipStream_t s,
                   uint64_t *gscratch, size_t slice_words, uint32_t scratch_blocks, hipEvent_t *ev, hipStream_t side,
-                  hipEvent_t fork, hipEvent_t join) {
+                  hipEvent_t fork, hipEvent_t join, hipStream_t side2 = nullptr, hipEvent_t fork2 = nullptr,
+                  hipEvent_t join2 = nullptr) {
     const kc_tuning_t &tu = kc_tuning_now();
     // The one-wave tier goes first, on the side stream from k = 7 on (when there is one
     // and the other tiers have roots): the tiers share no root and no counter, so the
@@ -1767,7 +1768,7 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
             return best;
         };
         auto launch_wg = [&](const uint32_t *queue, uint32_t count, const uint64_t *items, uint32_t *next,
-                             uint32_t dmax) {
+                             uint32_t dmax, bool items_l2, hipStream_t st) {
             CountParams p = base;
             p.queue = queue;
             p.count = count;
@@ -1779,22 +1780,36 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
             const WgLayout L = wg_layout(p.dcap, K, nw, wg_lean(MODE, p.colored));
             uint32_t blocks = (uint32_t)di.cus * sh.per_cu;
             if (blocks > count) blocks = count;
-            const bool l2 = items && q.wg_l2;
+            const bool l2 = items && items_l2;
             if (nw == 16 && l2)
-                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 16, true>), dim3(blocks), dim3(1024), L.bytes, s, p);
+                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 16, true>), dim3(blocks), dim3(1024), L.bytes, st, p);
             else if (nw == 16)
-                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 16, false>), dim3(blocks), dim3(1024), L.bytes, s, p);
+                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 16, false>), dim3(blocks), dim3(1024), L.bytes, st, p);
             else if (nw == 8 && l2)
-                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 8, true>), dim3(blocks), dim3(512), L.bytes, s, p);
+                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 8, true>), dim3(blocks), dim3(512), L.bytes, st, p);
             else if (nw == 8)
-                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 8, false>), dim3(blocks), dim3(512), L.bytes, s, p);
+                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 8, false>), dim3(blocks), dim3(512), L.bytes, st, p);
             else if (l2)
-                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 4, true>), dim3(blocks), dim3(256), L.bytes, s, p);
+                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 4, true>), dim3(blocks), dim3(256), L.bytes, st, p);
             else
-                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 4, false>), dim3(blocks), dim3(256), L.bytes, s, p);
+                hipLaunchKernelGGL((k_count_wg<K, false, MODE, 4, false>), dim3(blocks), dim3(256), L.bytes, st, p);
         };
-        if (q.wg_items) {
-            launch_wg(q.ptr[1], q.wg_item_count, q.wg_items, cursors + 1, q.max_d[1]);
+        if (q.wg_items && q.wg_items2) {
+            // the large roots' items with their large arena on the third stream, beside
+            // the small roots' items with a small arena (more blocks per CU) on s
+            const bool fork_ok = side2 && fork2 && join2;
+            hipStream_t sb = fork_ok ? side2 : s;
+            if (fork_ok) {
+                (void)hipEventRecord(fork2, s);
+                (void)hipStreamWaitEvent(side2, fork2, 0);
+            }
+            launch_wg(q.ptr[1], q.wg_item_count, q.wg_items, cursors + 1, q.max_d[1], q.wg_l2, sb);
+            if (fork_ok) (void)hipEventRecord(join2, side2);
+            launch_wg(q.ptr[1], q.wg_item_count2, q.wg_items2, cursors + 3 + KC_WG_CLASSES, q.wg_dmax2, q.wg_l2b,
+                      s);
+            if (fork_ok) (void)hipStreamWaitEvent(s, join2, 0);
+        } else if (q.wg_items) {
+            launch_wg(q.ptr[1], q.wg_item_count, q.wg_items, cursors + 1, q.max_d[1], q.wg_l2, s);
         } else if (q.wg_ncls > 1) {
             // Consecutive out-degree classes (largest first) grouped into launches: a
             // class joins the current group when a launch of its own would hold no
@@ -1810,7 +1825,7 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
                         continue;
                     }
                 }
-                launch_wg(q.ptr[1] + q.wg_cls_off[g0], cnt, nullptr, cursors + 3 + g0, q.wg_cls_dmax[g0]);
+                launch_wg(q.ptr[1] + q.wg_cls_off[g0], cnt, nullptr, cursors + 3 + g0, q.wg_cls_dmax[g0], false, s);
                 if (c < q.wg_ncls) {
                     g0 = c;
                     cnt = q.wg_cls_cnt[c];
@@ -1818,7 +1833,7 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
                 }
             }
         } else {
-            launch_wg(q.ptr[1], q.count[1], nullptr, cursors + 1, q.max_d[1]);
+            launch_wg(q.ptr[1], q.count[1], nullptr, cursors + 1, q.max_d[1], false, s);
         }
     }
     if (ev) (void)hipEventRecord(ev[2], s);
@@ -1975,9 +1990,10 @@ kc_status kc_stage(kc_graph *g, int wd) {
     kc_cache_free(g->wbits, s);
     kc_cache_free(g->woff, s);
     kc_cache_free(g->wq, s);
+    kc_cache_free(g->wq2, s);
     kc_cache_free(g->wedges, s);
     g->lrows = g->wbits = g->woff = nullptr;
-    g->wq = nullptr;
+    g->wq = g->wq2 = nullptr;
     g->wedges = nullptr;
     g->wq_ready = 0;
     g->staged = 0;
@@ -2050,6 +2066,15 @@ uint32_t kc_lds_dcap(int device, int k) {
 
 size_t kc_scratch_slice_words(uint32_t dmax, int k) { return (wg_layout(dmax, k).bytes + 7) / 8; }
 
+// Four-wave workgroup blocks per CU that LDS allows when the arena holds out-degree d
+// (an uncoloured count from the staged cache).
+uint32_t kc_wg_blocks_per_cu(int device, int k, uint32_t d) {
+    const DevInfo di = dev_info(device);
+    const size_t per_block = wg_layout(d < 65 ? 65 : d, k, 4, wg_lean(MODE_CACHED, false)).bytes +
+                             wg_static_lds(k, 4) + 1024;
+    return (uint32_t)(di.lds_max / per_block);
+}
+
 // Global-memory slices of the scratch tier for this queue.
 kc_status kc_count_scratch(const kc_graph *g, const kc_queue &q, int k, kc_tmp &gscr, size_t &slice_words,
                            uint32_t &blocks) {
@@ -2072,8 +2097,9 @@ kc_status kc_count_scratch(const kc_graph *g, const kc_queue &q, int k, kc_tmp &
 kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_args &a, uint64_t *res,
                           unsigned long long *gtotals, uint32_t ngraphs, const uint32_t *graph_of, uint64_t *gscratch,
                           size_t slice_words, uint32_t scratch_blocks, hipStream_t s, hipEvent_t *tier_ev,
-                          bool use_side) {
+                          bool use_side, bool use_side2) {
     hipStream_t side = use_side ? g->side : nullptr;
+    hipStream_t side2 = use_side2 ? g->side2 : nullptr;
     const DevInfo di = dev_info(g->device);
     hipLaunchKernelGGL(k_fill_u64, dim3((KC_RES_WORDS + 63) / 64), dim3(64), 0, s, res, (size_t)KC_RES_WORDS, 0ull);
     if (gtotals)
@@ -2121,7 +2147,7 @@ kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_a
     case KK:                                                                                                 \
         if (a.cached)                                                                                        \
             launch_tiers<KK, MODE_CACHED>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev, \
-                                          side, g->fork, g->join);                                           \
+                                          side, g->fork, g->join, side2, g->fork2, g->join2);                \
         else                                                                                                 \
             launch_tiers<KK, MODE_STAGE>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev,  \
                                          side, g->fork, g->join);                                            \
@@ -2231,6 +2257,18 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
     // the second stream (one-wave tier beside the others, k >= 7) is created on first use,
     // so handles that never count at k >= 7 (batches of many graphs) hold none
     const bool side = a.k >= 7;
+    const bool side2 = q.wg_items2 != nullptr;
+    if (side2 && !g->side2) {
+        kc_graph *gm = const_cast<kc_graph *>(g);
+        KC_HIP(hipStreamCreateWithFlags(&gm->side2, hipStreamNonBlocking));  // default priority
+        KC_HIP(hipEventCreateWithFlags(&gm->fork2, hipEventDisableTiming));
+        KC_HIP(hipEventCreateWithFlags(&gm->join2, hipEventDisableTiming));
+        if (gc == &view) {
+            view.side2 = g->side2;
+            view.fork2 = g->fork2;
+            view.join2 = g->join2;
+        }
+    }
     if (side && !g->side) {
         kc_graph *gm = const_cast<kc_graph *>(g);
         KC_HIP(hipStreamCreateWithFlags(&gm->side, hipStreamNonBlocking));  // default priority
@@ -2244,7 +2282,7 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
     }
     hipEvent_t tev[6] = {g->ev[2], g->ev[3], g->ev[4], g->ev[5], g->ev[6], g->ev[7]};
     KC_TRY(kc_count_launch(gc, q, ac, g->d_res, nullptr, 0, nullptr, gscr.as<uint64_t>(), slice_words, scratch_blocks,
-                           s, tev, side));
+                           s, tev, side, side2));
     uint64_t *h_res = kc_pinned_scratch();
     KC_HIP(hipMemcpyAsync(h_res, g->d_res, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     KC_TRY(kc_sync(s));

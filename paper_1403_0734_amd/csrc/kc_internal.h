@@ -128,6 +128,12 @@ struct kc_graph {
     uint32_t wq_first = 0, wq_roots = 0, wq_count = 0;
     uint64_t *wq = nullptr;
     bool wq_l2 = false;          // wq holds two-level items
+    // With wq_dsplit > 0, wq holds the items of the tier's roots above out-degree
+    // wq_dsplit and wq2 those of the others (each launched with an arena of its own size).
+    uint32_t wq_dsplit = 0;
+    uint64_t *wq2 = nullptr;
+    uint32_t wq2_count = 0;
+    bool wq2_l2 = false;
     uint32_t *wedges = nullptr;  // edges of G+(u) by rank, written when staging (roots above stage_wd)
 
     uint64_t serial = 0;  // unique per handle (batch plans are keyed by it)
@@ -136,6 +142,10 @@ struct kc_graph {
     // workgroup and scratch tiers (fork / join events, no timing)
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    // third stream: the workgroup tier's large roots beside its small ones (created on
+    // first use)
+    hipStream_t side2 = nullptr;
+    hipEvent_t fork2 = nullptr, join2 = nullptr;
     float t_schedule = 0.f, t_count = 0.f, t_total = 0.f;
     float t_tier[3] = {0.f, 0.f, 0.f};  // wave, workgroup, scratch kernels of the last count
     hipEvent_t sev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // around the staging tiers
@@ -174,6 +184,8 @@ struct kc_count_args {
 kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *total, int *overflow);
 struct kc_queue;
 uint32_t kc_lds_dcap(int device, int k);
+// Four-wave workgroup blocks per CU that LDS allows for an arena holding out-degree d.
+uint32_t kc_wg_blocks_per_cu(int device, int k, uint32_t d);
 kc_status kc_count_scratch(const kc_graph *g, const kc_queue &q, int k, kc_tmp &gscr, size_t &slice_words,
                            uint32_t &blocks);
 // tier_ev (may be null): 6 events: [0] before the scratch tier, [1] after it (before
@@ -182,7 +194,7 @@ kc_status kc_count_scratch(const kc_graph *g, const kc_queue &q, int k, kc_tmp &
 kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_args &a, uint64_t *res,
                           unsigned long long *gtotals, uint32_t ngraphs, const uint32_t *graph_of, uint64_t *gscratch,
                           size_t slice_words, uint32_t scratch_blocks, hipStream_t s,
-                          hipEvent_t *tier_ev = nullptr, bool use_side = false);
+                          hipEvent_t *tier_ev = nullptr, bool use_side = false, bool use_side2 = false);
 
 // Stage every root's G+(u) into the handle's cache (one-wave tier split at wd); the
 // handle is left uncached (staged = -1) when the cache would not fit.
@@ -224,6 +236,12 @@ struct kc_queue {
     const uint64_t *wg_items = nullptr;  // workgroup tier as split items (see KC_ITEM_LEVEL2 below)
     uint32_t wg_item_count = 0;
     bool wg_l2 = false;                  // the items include two-level items
+    // the tier's roots of out-degree up to wg_dmax2 as items of their own (after the
+    // larger roots' wg_items, which then cover only those above wg_dmax2)
+    const uint64_t *wg_items2 = nullptr;
+    uint32_t wg_item_count2 = 0;
+    bool wg_l2b = false;
+    uint32_t wg_dmax2 = 0;
     const uint32_t *ptr[3];    // root ranks of each tier (wave, workgroup, scratch), heaviest first
     uint32_t count[3];         // roots per tier
     uint32_t max_d[3];         // largest out-degree in each tier

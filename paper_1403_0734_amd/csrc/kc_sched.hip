@@ -398,16 +398,29 @@ kc_status build_items(const Est &E, uint32_t cnt, hipStream_t s, uint64_t **item
     return KC_OK;
 }
 
-kc_status build_work_items(kc_graph *g, uint32_t first, uint32_t cnt) {
+// The workgroup tier's items for its cnt roots from queue position first (out-degree
+// descending), split at out-degree dsplit when that leaves roots on both sides: the
+// nbig roots above it in g->wq, the rest in g->wq2.
+kc_status build_work_items(kc_graph *g, uint32_t first, uint32_t cnt, uint32_t dsplit, uint32_t nbig) {
     hipStream_t s = g->stream;
     kc_cache_free(g->wq, s);
-    g->wq = nullptr;
-    g->wq_count = 0;
+    kc_cache_free(g->wq2, s);
+    g->wq = g->wq2 = nullptr;
+    g->wq_count = g->wq2_count = 0;
+    g->wq_l2 = g->wq2_l2 = false;
     g->wq_ready = 0;
+    if (nbig == 0 || nbig >= cnt) dsplit = 0;
+    const uint32_t n1 = dsplit ? nbig : cnt;
     EstEdges E{g->dq + first, g->wedges, g->optr, g->wbits, g->woff};
     uint32_t bound = 0;
-    KC_TRY(build_items(E, cnt, s, &g->wq, &bound, &g->wq_l2));
+    KC_TRY(build_items(E, n1, s, &g->wq, &bound, &g->wq_l2));
     g->wq_count = bound;
+    if (dsplit) {
+        EstEdges E2{g->dq + first + nbig, g->wedges, g->optr, g->wbits, g->woff};
+        KC_TRY(build_items(E2, cnt - nbig, s, &g->wq2, &bound, &g->wq2_l2));
+        g->wq2_count = bound;
+    }
+    g->wq_dsplit = dsplit;
     g->wq_first = first;
     g->wq_roots = cnt;
     g->wq_ready = 1;
@@ -639,12 +652,47 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
         const char *wo = getenv("KC_WORK_ORDER");
         if (k >= 5 && q.count[1] && g->staged == 1 && g->stage_wd == wd && g->wedges && !(wo && wo[0] == '0')) {
             const uint32_t first = (uint32_t)(q.ptr[1] - g->dq);
-            const bool have = g->wq_ready && g->wq_first == first && g->wq_roots == q.count[1];
+            // When the tier's largest arena leaves at most two blocks per CU, the roots
+            // above dsplit get items of their own, launched with that arena beside the
+            // others' smaller one: dsplit is the largest out-degree whose arena allows three
+            // more blocks per CU.  R-MAT 22 at k = 5 (out-degrees to 1031, one block per
+            // CU): 1.28 s in one list, 0.61-0.64 s split at 512-640.  KC_WG_DSPLIT (test
+            // hook) sets it (0: one list).
+            const char *ds = getenv("KC_WG_DSPLIT");
+            uint32_t dsplit = 0;
+            if (ds) {
+                dsplit = (uint32_t)atoi(ds);
+            } else {
+                const uint32_t bt = kc_wg_blocks_per_cu(g->device, k, top);
+                if (bt <= 2) {
+                    uint32_t lo = (uint32_t)wd, hi = top;  // blocks(lo) >= bt + 3 > blocks(hi)
+                    if (kc_wg_blocks_per_cu(g->device, k, lo + 1) >= bt + 3) {
+                        while (hi - lo > 1) {
+                            const uint32_t mid = (lo + hi) / 2;
+                            if (kc_wg_blocks_per_cu(g->device, k, mid) >= bt + 3) lo = mid; else hi = mid;
+                        }
+                        dsplit = lo;
+                    }
+                }
+            }
+            if (dsplit <= (uint32_t)wd || dsplit >= top) dsplit = 0;
+            uint32_t nbig = 0;
+            if (dsplit)
+                for (uint32_t d = dsplit + 1; d <= top; ++d) nbig += (uint32_t)hist[d];
+            if (nbig == 0 || nbig >= q.count[1]) dsplit = 0;
+            const bool have = g->wq_ready && g->wq_first == first && g->wq_roots == q.count[1] &&
+                              g->wq_dsplit == dsplit;
             if (!have && no_alloc) return KC_OK;  // whole roots
-            if (!have) KC_TRY(build_work_items(gm, first, q.count[1]));
+            if (!have) KC_TRY(build_work_items(gm, first, q.count[1], dsplit, nbig));
             q.wg_items = g->wq;
             q.wg_item_count = g->wq_count;
             q.wg_l2 = g->wq_l2;
+            if (g->wq_dsplit) {
+                q.wg_items2 = g->wq2;
+                q.wg_item_count2 = g->wq2_count;
+                q.wg_l2b = g->wq2_l2;
+                q.wg_dmax2 = g->wq_dsplit;
+            }
             return KC_OK;
         }
         if (no_alloc) return KC_OK;

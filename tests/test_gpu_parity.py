@@ -302,6 +302,8 @@ ITEM_MODES = {
     "degree split": {"KC_WORK_ORDER": "0"},
     "degree split, per-call staging": {"KC_STAGE_CACHE": "0", "KC_DEGREE_SPLIT": "5"},
     "whole roots": {"KC_WORK_ORDER": "0", "KC_DEGREE_SPLIT": "0"},
+    "two lists split at out-degree 96": {"KC_WG_DSPLIT": "96"},
+    "two lists split at out-degree 100, per-call staging": {"KC_WG_DSPLIT": "100", "KC_STAGE_CACHE": "0"},
 }
 
 
@@ -327,6 +329,29 @@ def test_workgroup_items(monkeypatch, mode):
                 e = K.kc_count_colored(h, k, 2, 5, scheme)
                 assert e.raw == og.count_colored(k, 2, 5, scheme), (el.name, k, scheme)
         _close(h)
+
+
+@pytest.mark.parametrize("dsplit", [None, "0", "300", "850"])
+def test_workgroup_split_by_outdegree(monkeypatch, dsplit):
+    """Roots of out-degree 900 beside roots below 100 in the workgroup tier: at k >= 5
+    the default rule gives the large roots items of their own (one large arena per
+    block, few blocks per CU) beside the small roots' (small arena, many blocks),
+    launched side by side; forced split points and one list give the same counts."""
+    if dsplit is not None:
+        monkeypatch.setenv("KC_WG_DSPLIT", dsplit)
+    el = S.disjoint_union(S.hub_bipartite(880, 900, 0.03, 21), S.random_graph(300, 0.3, 22))
+    og = O.OracleGraph.from_edgelist(el)
+    h = device_graph(el)
+    assert K.kc_graph_info(h)[2] == og.max_outdeg() > 850
+    for k in (5, 6, 7):
+        announce(f"split by out-degree {dsplit} k={k}")
+        assert K.kc_count(h, k) == og.count(k), k
+    c, _ = per_root(h, el.n, 5)
+    assert np.array_equal(c, og.count_per_root(5))
+    for scheme in (K.KC_COLOR_PER_ROOT, K.KC_COLOR_GLOBAL):
+        e = K.kc_count_colored(h, 5, 2, 5, scheme)
+        assert e.raw == og.count_colored(5, 2, 5, scheme), scheme
+    _close(h)
 
 
 @pytest.mark.parametrize("p", [1.0, 0.5, 0.2])

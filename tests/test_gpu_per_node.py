@@ -39,7 +39,7 @@ def per_node(h, n, k):
     return c.cpu().numpy().view(np.uint64)[:n]
 
 
-def oracle_ks(og, budget=4e6):
+def oracle_ks(og, budget=1e7):
     """Clique sizes the oracle lists quickly (it visits every k-clique k times)."""
     out = []
     for k in range(1, K.KC_KMAX + 1):
@@ -56,8 +56,8 @@ CASES = [
     S.random_graph(300, 0.3, 3, dup_frac=0.1, loops=2),
     S.planted_small(400, 0.02, [list(range(0, 60, 2)), list(range(100, 190, 3)), list(range(5, 395, 5))], 4),
     S.disjoint_union(S.complete(20), S.complete_multipartite([4, 4, 4, 4]), S.random_graph(90, 0.4, 5)),
-    # wide roots: every node of A keeps B (300 / 1500 nodes) as its high neighbours
-    S.hub_bipartite(6, 300, 0.08, 1), S.hub_bipartite(3, 1500, 0.012, 2),
+    # wide roots: every node of A keeps B (300 / 600 nodes) as its high neighbours
+    S.hub_bipartite(290, 300, 0.05, 1), S.hub_bipartite(580, 600, 0.04, 2),
     G.chung_lu(20000, 2.1, 15.0, 800.0, 9),
 ]
 
