@@ -1674,13 +1674,19 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
                 per_cu = (uint32_t)occ;
             const uint32_t cap = (uint32_t)di.cus * per_cu;
             if (blocks > cap) blocks = cap;
-            // chunk size follows the work per root: staging (reads every out-list) takes
-            // half-size chunks, counts from the cache at k <= 5 (a few cheap passes per
-            // chunk) larger ones, so that fewer queue fetches stall the wave
+            // Chunk size (queue / (waves x divisor)) by clique size, measured on planted
+            // 4M and Chung-Lu 1M: staging takes half-size chunks; counts from the cache
+            // smaller chunks as the work per root grows up to k = 6 (the tier runs alone:
+            // planted k = 6, 4.2 ms at the base divisor, 1.3 ms at 4x).  From k = 7 the
+            // tier runs beside the workgroup tier, and larger chunks leave the latter more
+            // of the CUs early on: planted k = 8, workgroup tier 317 ms with the base
+            // divisor, 281 ms with half of it (the one-wave tier then ends at 152 ms,
+            // still first).
             const uint32_t cd = base.chunk_div;
             if (MODE == MODE_STORE) p.chunk_div = cd * 2;
-            else if (MODE == MODE_CACHED && K <= 4) p.chunk_div = cd / 4 ? cd / 4 : 1;
-            else if (MODE == MODE_CACHED && K == 5) p.chunk_div = cd / 2 ? cd / 2 : 1;
+            else if (MODE == MODE_CACHED && K == 5) p.chunk_div = cd * 2;
+            else if (MODE == MODE_CACHED && K == 6) p.chunk_div = cd * 4;
+            else if (MODE == MODE_CACHED && K >= 8) p.chunk_div = cd / 2 ? cd / 2 : 1;
             hipLaunchKernelGGL((k_count_wave<K, MODE>), dim3(blocks), dim3(WG), 0, ws, p);
         }
         if (ev) (void)hipEventRecord(ev[5], ws);
