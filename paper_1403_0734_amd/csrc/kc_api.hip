@@ -117,9 +117,6 @@ void kc_graph_destroy(kc_graph *g) {
     if (g->fork) (void)hipEventDestroy(g->fork);
     if (g->join) (void)hipEventDestroy(g->join);
     if (g->side) (void)hipStreamDestroy(g->side);
-    if (g->fork2) (void)hipEventDestroy(g->fork2);
-    if (g->join2) (void)hipEventDestroy(g->join2);
-    if (g->side2) (void)hipStreamDestroy(g->side2);
     delete g;
 }
 

@@ -621,10 +621,8 @@ struct WaveStage {
 static_assert(offsetof(WaveStage, rows) == 0 && offsetof(LocalArea<1>, rows) == 0,
               "staging rows must alias the local graph's rows");
 
-// The one-wave tier counts in place from k = 8 on.  At k = 7 the in-place kernel's
-// extra registers and smaller local areas let more one-wave blocks share the CUs
-// with the workgroup tier that runs beside it, and the workgroup tier, which takes
-// longer, slows by more than the one-wave tier gains.
+// The one-wave tier counts in place from k = 8 on (planted 4M, k = 8: 169 ms to 97 ms
+// with the tier's base chunk size); at k = 7 it made no measurable difference.
 constexpr bool wave_inplace(int k) { return k >= 8; }
 constexpr int wave_stack(int k) {
     return wave_inplace(k) ? (k - 5 > 1 ? k - 5 : 1) : (k - 4 > 1 ? k - 4 : 1);
@@ -1644,20 +1642,18 @@ DevInfo dev_info(int device) {
 
 template <int K, int MODE>
 void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors, const DevInfo &di, hipStream_t s,
-                  uint64_t *gscratch, size_t slice_words, uint32_t scratch_blocks, hipEvent_t *ev, hipStream_t side,
-                  hipEvent_t fork, hipEvent_t join, hipStream_t side2 = nullptr, hipEvent_t fork2 = nullptr,
-                  hipEvent_t join2 = nullptr) {
+                  uint64_t *gscratch, size_t slice_words, uint32_t scratch_blocks, hipEvent_t *ev,
+                  hipStream_t side = nullptr, hipEvent_t fork = nullptr, hipEvent_t join = nullptr) {
     const kc_tuning_t &tu = kc_tuning_now();
-    // The one-wave tier goes first, on the side stream from k = 7 on (when there is one
-    // and the other tiers have roots): the tiers share no root and no counter, so the
-    // wave tier's blocks fill what the long workgroup launches leave free.  Measured:
-    // planted 4M at k = 8 takes 355 ms instead of 509; at k <= 6 the two tiers slow
-    // each other down (Chung-Lu 1M: no gain over the step, k = 5 and staging slower).
+    // Scratch tier, workgroup tier, then the one-wave tier, on s.  (The one-wave tier
+    // beside the others on a second stream was faster at k >= 7 before the workgroup
+    // arena shrank for cached counts; now the workgroup tier runs faster alone and
+    // the one-wave tier after it in small chunks: planted 4M k = 7 / 8, 138 / 268 ms in
+    // sequence against 154 / 286 ms side by side.)  side, fork, join: the third
+    // stream for the workgroup tier's large roots (may be null).
     // ev: [0] scratch start, [1] scratch end / workgroup start, [2] workgroup end,
-    // [3] all done (after the join), [4] [5] the one-wave tier.
-    const bool split =
-        K >= 7 && MODE != MODE_STORE && side && fork && join && q.count[0] && (q.count[1] || q.count[2]);
-    hipStream_t ws = split ? side : s;
+    // [3] all done, [4] [5] the one-wave tier.
+    hipStream_t ws = s;
     auto launch_wave = [&]() {
         if (ev) (void)hipEventRecord(ev[4], ws);
         if (q.count[0]) {
@@ -1676,27 +1672,17 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
             if (blocks > cap) blocks = cap;
             // Chunk size (queue / (waves x divisor)) by clique size, measured on planted
             // 4M and Chung-Lu 1M: staging takes half-size chunks; counts from the cache
-            // smaller chunks as the work per root grows up to k = 6 (the tier runs alone:
-            // planted k = 6, 4.2 ms at the base divisor, 1.3 ms at 4x).  From k = 7 the
-            // tier runs beside the workgroup tier, and larger chunks leave the latter more
-            // of the CUs early on: planted k = 8, workgroup tier 317 ms with the base
-            // divisor, 281 ms with half of it (the one-wave tier then ends at 152 ms,
-            // still first).
+            // smaller chunks as the work per root grows (planted k = 6, 4.2 ms at the
+            // base divisor, 1.3 ms at 4x; k = 8, 96 ms at the base, 17 ms at 8x).
             const uint32_t cd = base.chunk_div;
             if (MODE == MODE_STORE) p.chunk_div = cd * 2;
             else if (MODE == MODE_CACHED && K == 5) p.chunk_div = cd * 2;
             else if (MODE == MODE_CACHED && K == 6) p.chunk_div = cd * 4;
-            else if (MODE == MODE_CACHED && K >= 8) p.chunk_div = cd / 2 ? cd / 2 : 1;
+            else if (MODE == MODE_CACHED && K >= 7) p.chunk_div = cd * 8;
             hipLaunchKernelGGL((k_count_wave<K, MODE>), dim3(blocks), dim3(WG), 0, ws, p);
         }
         if (ev) (void)hipEventRecord(ev[5], ws);
     };
-    if (split) {
-        (void)hipEventRecord(fork, s);
-        (void)hipStreamWaitEvent(side, fork, 0);
-        launch_wave();
-        (void)hipEventRecord(join, side);
-    }
     if (ev) (void)hipEventRecord(ev[0], s);
     // scratch tier first: the largest roots
     if (q.count[2]) {
@@ -1803,17 +1789,17 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
         if (q.wg_items && q.wg_items2) {
             // the large roots' items with their large arena on the third stream, beside
             // the small roots' items with a small arena (more blocks per CU) on s
-            const bool fork_ok = side2 && fork2 && join2;
-            hipStream_t sb = fork_ok ? side2 : s;
+            const bool fork_ok = side && fork && join;
+            hipStream_t sb = fork_ok ? side : s;
             if (fork_ok) {
-                (void)hipEventRecord(fork2, s);
-                (void)hipStreamWaitEvent(side2, fork2, 0);
+                (void)hipEventRecord(fork, s);
+                (void)hipStreamWaitEvent(side, fork, 0);
             }
             launch_wg(q.ptr[1], q.wg_item_count, q.wg_items, cursors + 1, q.max_d[1], q.wg_l2, sb);
-            if (fork_ok) (void)hipEventRecord(join2, side2);
+            if (fork_ok) (void)hipEventRecord(join, side);
             launch_wg(q.ptr[1], q.wg_item_count2, q.wg_items2, cursors + 3 + KC_WG_CLASSES, q.wg_dmax2, q.wg_l2b,
                       s);
-            if (fork_ok) (void)hipStreamWaitEvent(s, join2, 0);
+            if (fork_ok) (void)hipStreamWaitEvent(s, join, 0);
         } else if (q.wg_items) {
             launch_wg(q.ptr[1], q.wg_item_count, q.wg_items, cursors + 1, q.max_d[1], q.wg_l2, s);
         } else if (q.wg_ncls > 1) {
@@ -1843,8 +1829,7 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
         }
     }
     if (ev) (void)hipEventRecord(ev[2], s);
-    if (split) (void)hipStreamWaitEvent(s, join, 0);
-    else launch_wave();  // after the other tiers, on the same stream
+    launch_wave();
     if (ev) (void)hipEventRecord(ev[3], s);
 }
 
@@ -2103,9 +2088,8 @@ kc_status kc_count_scratch(const kc_graph *g, const kc_queue &q, int k, kc_tmp &
 kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_args &a, uint64_t *res,
                           unsigned long long *gtotals, uint32_t ngraphs, const uint32_t *graph_of, uint64_t *gscratch,
                           size_t slice_words, uint32_t scratch_blocks, hipStream_t s, hipEvent_t *tier_ev,
-                          bool use_side, bool use_side2) {
+                          bool use_side) {
     hipStream_t side = use_side ? g->side : nullptr;
-    hipStream_t side2 = use_side2 ? g->side2 : nullptr;
     const DevInfo di = dev_info(g->device);
     hipLaunchKernelGGL(k_fill_u64, dim3((KC_RES_WORDS + 63) / 64), dim3(64), 0, s, res, (size_t)KC_RES_WORDS, 0ull);
     if (gtotals)
@@ -2142,8 +2126,7 @@ kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_a
     if (a.store) {
         // staging into the cache does not depend on k; its total is q_3 (the edges of
         // every G+(u)), kept in res as a count would leave it
-        launch_tiers<3, MODE_STORE>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev, side, g->fork,
-                                    g->join);
+        launch_tiers<3, MODE_STORE>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev);
         if (!gtotals) hipLaunchKernelGGL(k_total_slots, dim3(1), dim3(64), 0, s, res);
         KC_HIP(hipGetLastError());
         return KC_OK;
@@ -2153,10 +2136,9 @@ kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_a
     case KK:                                                                                                 \
         if (a.cached)                                                                                        \
             launch_tiers<KK, MODE_CACHED>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev, \
-                                          side, g->fork, g->join, side2, g->fork2, g->join2);                \
+                                          side, g->fork, g->join);                                           \
         else                                                                                                 \
-            launch_tiers<KK, MODE_STAGE>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev,  \
-                                         side, g->fork, g->join);                                            \
+            launch_tiers<KK, MODE_STAGE>(p, q, cursors, di, s, gscratch, slice_words, scratch_blocks, tier_ev); \
         break;
         KC_CASE(3)
         KC_CASE(4)
@@ -2260,21 +2242,9 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
         view.wbits_raw = g->wbits;  // work items were split on the bitmaps as staged
         gc = &view;
     }
-    // the second stream (one-wave tier beside the others, k >= 7) is created on first use,
-    // so handles that never count at k >= 7 (batches of many graphs) hold none
-    const bool side = a.k >= 7;
-    const bool side2 = q.wg_items2 != nullptr;
-    if (side2 && !g->side2) {
-        kc_graph *gm = const_cast<kc_graph *>(g);
-        KC_HIP(hipStreamCreateWithFlags(&gm->side2, hipStreamNonBlocking));  // default priority
-        KC_HIP(hipEventCreateWithFlags(&gm->fork2, hipEventDisableTiming));
-        KC_HIP(hipEventCreateWithFlags(&gm->join2, hipEventDisableTiming));
-        if (gc == &view) {
-            view.side2 = g->side2;
-            view.fork2 = g->fork2;
-            view.join2 = g->join2;
-        }
-    }
+    // the second stream (the workgroup tier's large roots beside its small ones) is
+    // created on first use, so handles that never split their tier hold none
+    const bool side = q.wg_items2 != nullptr;
     if (side && !g->side) {
         kc_graph *gm = const_cast<kc_graph *>(g);
         KC_HIP(hipStreamCreateWithFlags(&gm->side, hipStreamNonBlocking));  // default priority
@@ -2288,7 +2258,7 @@ kc_status kc_count_impl(const kc_graph *g, const kc_count_args &a, uint64_t *tot
     }
     hipEvent_t tev[6] = {g->ev[2], g->ev[3], g->ev[4], g->ev[5], g->ev[6], g->ev[7]};
     KC_TRY(kc_count_launch(gc, q, ac, g->d_res, nullptr, 0, nullptr, gscr.as<uint64_t>(), slice_words, scratch_blocks,
-                           s, tev, side, side2));
+                           s, tev, side));
     uint64_t *h_res = kc_pinned_scratch();
     KC_HIP(hipMemcpyAsync(h_res, g->d_res, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     KC_TRY(kc_sync(s));

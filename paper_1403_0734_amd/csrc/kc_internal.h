@@ -138,14 +138,10 @@ struct kc_graph {
 
     uint64_t serial = 0;  // unique per handle (batch plans are keyed by it)
     hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    // second stream of the handle: the one-wave tier runs on it beside the
-    // workgroup and scratch tiers (fork / join events, no timing)
+    // second stream of the handle: the workgroup tier's large roots run on it beside
+    // its small ones (fork / join events, no timing; created on first use)
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
-    // third stream: the workgroup tier's large roots beside its small ones (created on
-    // first use)
-    hipStream_t side2 = nullptr;
-    hipEvent_t fork2 = nullptr, join2 = nullptr;
     float t_schedule = 0.f, t_count = 0.f, t_total = 0.f;
     float t_tier[3] = {0.f, 0.f, 0.f};  // wave, workgroup, scratch kernels of the last count
     hipEvent_t sev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // around the staging tiers
@@ -189,12 +185,12 @@ uint32_t kc_wg_blocks_per_cu(int device, int k, uint32_t d);
 kc_status kc_count_scratch(const kc_graph *g, const kc_queue &q, int k, kc_tmp &gscr, size_t &slice_words,
                            uint32_t &blocks);
 // tier_ev (may be null): 6 events: [0] before the scratch tier, [1] after it (before
-// the workgroup tier), [2] after the workgroup tier, [3] after every tier (the join),
+// the workgroup tier), [2] after the workgroup tier, [3] after every tier,
 // [4] [5] around the one-wave tier.
 kc_status kc_count_launch(const kc_graph *g, const kc_queue &q, const kc_count_args &a, uint64_t *res,
                           unsigned long long *gtotals, uint32_t ngraphs, const uint32_t *graph_of, uint64_t *gscratch,
                           size_t slice_words, uint32_t scratch_blocks, hipStream_t s,
-                          hipEvent_t *tier_ev = nullptr, bool use_side = false, bool use_side2 = false);
+                          hipEvent_t *tier_ev = nullptr, bool use_side = false);
 
 // Stage every root's G+(u) into the handle's cache (one-wave tier split at wd); the
 // handle is left uncached (staged = -1) when the cache would not fit.
