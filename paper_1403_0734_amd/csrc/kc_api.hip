@@ -107,6 +107,7 @@ void kc_graph_destroy(kc_graph *g) {
     for (auto &L : g->lq) {
         kc_cache_free(L.queue, g->stream);
         kc_cache_free(L.items, g->stream);
+        kc_cache_free(L.items2, g->stream);
     }
     (void)kc_sync(g->stream);
     delete[] g->dq_hist;

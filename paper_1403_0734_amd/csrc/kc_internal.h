@@ -95,6 +95,11 @@ struct kc_graph {
         uint64_t *items = nullptr;   // workgroup tier as split items (k >= 5)
         uint32_t item_count = 0;
         bool l2 = false;             // the items include two-level items
+        // with dsplit > 0: items cover the roots above out-degree dsplit, items2 the rest
+        uint32_t dsplit = 0;
+        uint64_t *items2 = nullptr;
+        uint32_t item_count2 = 0;
+        bool l2b = false;
         uint32_t count[3] = {0, 0, 0}, max_d[3] = {0, 0, 0};  // kc_queue order: wave, workgroup, scratch
     } lq[KC_KMAX + 1];
 

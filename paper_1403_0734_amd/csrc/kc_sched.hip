@@ -501,6 +501,39 @@ static uint32_t promote_outdeg(int k, float promote, uint32_t lo, uint32_t hi) {
     return hi + 1;
 }
 
+// Out-degree at which the workgroup tier's roots split into two item lists, each
+// launched with an arena of its own size (0: one list).  The roots above half the
+// tier's largest out-degree get items of their own, launched with an arena of that
+// size on a second stream beside the others' items with an arena of half the size
+// (about a quarter of the bytes: more blocks per CU).  Measured split points: R-MAT 22
+// k = 5 (out-degrees to 1031): one list 1.28 s, 384 / 512 / 640 / 768: 641 / 609 / 641
+// / 815 ms; planted 4M k = 5..8 (to 519): one list 16.9 / 42.7 / 138 / 266 ms, 256:
+// 16.1 / 40.9 / 136 / 259 ms, 160 or 400: between.  KC_WG_DSPLIT (test hook) sets it.
+static uint32_t choose_dsplit(const kc_graph *g, int k, uint32_t wd, uint32_t top) {
+    const char *ds = getenv("KC_WG_DSPLIT");
+    uint32_t dsplit = 0;
+    if (ds)
+        dsplit = (uint32_t)atoi(ds);
+    else if (top > 2u * wd && kc_wg_blocks_per_cu(g->device, k, top / 2) > kc_wg_blocks_per_cu(g->device, k, top))
+        dsplit = top / 2;
+    return dsplit > wd && dsplit < top ? dsplit : 0u;
+}
+
+// stable partition of n learned keys: those of roots above out-degree dsplit first
+__global__ void k_part_flags(const uint64_t *keys, uint32_t n, const uint64_t *optr, uint32_t dsplit,
+                             uint32_t *flag) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t r = (uint32_t)keys[i];
+    flag[i] = optr[r + 1] - optr[r] > dsplit ? 1u : 0u;
+}
+__global__ void k_part_scatter(const uint64_t *keys, uint32_t n, const uint32_t *flag, const uint32_t *pos,
+                               const uint32_t *nbig, uint64_t *out) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[flag[i] ? pos[i] : *nbig + (uint32_t)i - pos[i]] = keys[i];
+}
+
 // Learned queue of clique size k (cached on the handle): candidates are the roots
 // above the one-wave limit and the one-wave roots whose work bound reaches the
 // promotion threshold, a prefix of the degree queue (sorted by out-degree).
@@ -519,6 +552,7 @@ static kc_status build_learned(kc_graph *g, int k, uint32_t wd, uint32_t dcap, k
     }
     kc_cache_free(L.queue, s);
     kc_cache_free(L.items, s);
+    kc_cache_free(L.items2, s);
     L = kc_graph::LearnedQueue();
     KC_TRY(kc_dev_alloc((void **)&L.queue, (size_t)(active ? active : 1) * 4, s));
     uint32_t h_stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -553,8 +587,42 @@ static kc_status build_learned(kc_graph *g, int k, uint32_t wd, uint32_t dcap, k
     L.max_d[0] = wmax;
     if (k >= 5 && L.count[1]) {
         const bool bits = g->staged == 1 && g->stage_wd == (int)wd && g->wbits;
-        EstLearned E{keys.as<uint64_t>() + L.count[2], g->optr, bits ? g->wbits : nullptr, bits ? g->woff : nullptr};
-        KC_TRY(build_items(E, L.count[1], s, &L.items, &L.item_count, &L.l2));
+        const uint64_t *wk = keys.as<uint64_t>() + L.count[2];  // the workgroup tier, in priority order
+        const uint32_t c1 = L.count[1];
+        uint32_t dsplit = choose_dsplit(g, k, wd, L.max_d[1]);
+        uint32_t nbig = 0;
+        kc_tmp part, flag, pos, tot;
+        if (dsplit) {
+            // the tier's roots above dsplit first, each part in priority order
+            KC_TRY(kc_tmp_alloc(part, (size_t)c1 * 8, s));
+            KC_TRY(kc_tmp_alloc(flag, (size_t)c1 * 4, s));
+            KC_TRY(kc_tmp_alloc(pos, (size_t)c1 * 4, s));
+            KC_TRY(kc_tmp_alloc(tot, 4, s));
+            hipLaunchKernelGGL(k_part_flags, dim3(grid_for(c1)), dim3(T), 0, s, wk, c1, (const uint64_t *)g->optr,
+                               dsplit, flag.as<uint32_t>());
+            KC_HIP(hipGetLastError());
+            KC_TRY(kc_scan_excl_u32(flag.as<uint32_t>(), pos.as<uint32_t>(), c1, tot.as<uint32_t>(), s));
+            hipLaunchKernelGGL(k_part_scatter, dim3(grid_for(c1)), dim3(T), 0, s, wk, c1,
+                               (const uint32_t *)flag.as<uint32_t>(), (const uint32_t *)pos.as<uint32_t>(),
+                               (const uint32_t *)tot.as<uint32_t>(), part.as<uint64_t>());
+            KC_HIP(hipGetLastError());
+            uint32_t *h = (uint32_t *)kc_pinned_scratch();
+            KC_HIP(hipMemcpyAsync(h, tot.p, 4, hipMemcpyDeviceToHost, s));
+            KC_TRY(kc_sync(s));
+            nbig = h[0];
+            if (nbig == 0 || nbig >= c1) dsplit = 0;
+        }
+        const uint64_t *wbits = bits ? g->wbits : nullptr, *woff = bits ? g->woff : nullptr;
+        if (dsplit) {
+            EstLearned E{part.as<uint64_t>(), g->optr, wbits, woff};
+            KC_TRY(build_items(E, nbig, s, &L.items, &L.item_count, &L.l2));
+            EstLearned E2{part.as<uint64_t>() + nbig, g->optr, wbits, woff};
+            KC_TRY(build_items(E2, c1 - nbig, s, &L.items2, &L.item_count2, &L.l2b));
+            L.dsplit = dsplit;
+        } else {
+            EstLearned E{wk, g->optr, wbits, woff};
+            KC_TRY(build_items(E, c1, s, &L.items, &L.item_count, &L.l2));
+        }
     }
     L.wd = (int)wd;
     L.dcap = dcap;
@@ -595,6 +663,12 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
         q.wg_items = L.items;
         q.wg_item_count = L.items ? L.item_count : 0;
         q.wg_l2 = L.l2;
+        if (L.dsplit) {
+            q.wg_items2 = L.items2;
+            q.wg_item_count2 = L.item_count2;
+            q.wg_l2b = L.l2b;
+            q.wg_dmax2 = L.dsplit;
+        }
         q.wg_ncls = 0;
         return KC_OK;
     }
@@ -652,30 +726,7 @@ kc_status kc_build_queue(const kc_graph *g, int k, int policy, uint32_t d_lds_ma
         const char *wo = getenv("KC_WORK_ORDER");
         if (k >= 5 && q.count[1] && g->staged == 1 && g->stage_wd == wd && g->wedges && !(wo && wo[0] == '0')) {
             const uint32_t first = (uint32_t)(q.ptr[1] - g->dq);
-            // When the tier's largest arena leaves at most two blocks per CU, the roots
-            // above dsplit get items of their own, launched with that arena beside the
-            // others' smaller one: dsplit is the largest out-degree whose arena allows three
-            // more blocks per CU.  R-MAT 22 at k = 5 (out-degrees to 1031, one block per
-            // CU): 1.28 s in one list, 0.61-0.64 s split at 512-640.  KC_WG_DSPLIT (test
-            // hook) sets it (0: one list).
-            const char *ds = getenv("KC_WG_DSPLIT");
-            uint32_t dsplit = 0;
-            if (ds) {
-                dsplit = (uint32_t)atoi(ds);
-            } else {
-                const uint32_t bt = kc_wg_blocks_per_cu(g->device, k, top);
-                if (bt <= 2) {
-                    uint32_t lo = (uint32_t)wd, hi = top;  // blocks(lo) >= bt + 3 > blocks(hi)
-                    if (kc_wg_blocks_per_cu(g->device, k, lo + 1) >= bt + 3) {
-                        while (hi - lo > 1) {
-                            const uint32_t mid = (lo + hi) / 2;
-                            if (kc_wg_blocks_per_cu(g->device, k, mid) >= bt + 3) lo = mid; else hi = mid;
-                        }
-                        dsplit = lo;
-                    }
-                }
-            }
-            if (dsplit <= (uint32_t)wd || dsplit >= top) dsplit = 0;
+            uint32_t dsplit = choose_dsplit(g, k, (uint32_t)wd, top);
             uint32_t nbig = 0;
             if (dsplit)
                 for (uint32_t d = dsplit + 1; d <= top; ++d) nbig += (uint32_t)hist[d];

@@ -286,6 +286,28 @@ def batch_graphs():
     return gs
 
 
+@pytest.mark.parametrize("dsplit", [None, "0", "300"])
+def test_learned_schedule_split_by_outdegree(stream, tmp_path, monkeypatch, dsplit):
+    """The learned queue's workgroup tier in two item lists by out-degree (default
+    rule, forced, or one list): roots of out-degree about 900 beside roots below 100."""
+    if dsplit is not None:
+        monkeypatch.setenv("KC_WG_DSPLIT", dsplit)
+    train = [graph_on(el, stream) for el in training_graphs()[:2]]
+    wpath = str(tmp_path / "w.bin")
+    K.kc_train_schedule(train, 7, 5, 3, wpath)
+    el = S.disjoint_union(S.hub_bipartite(880, 900, 0.03, 21), S.random_graph(300, 0.3, 22))
+    og = O.OracleGraph.from_edgelist(el)
+    h = graph_on(el, stream)
+    K.kc_set_schedule(h, K.KC_SCHED_LEARNED, wpath)
+    for k in (5, 6, 7):
+        announce(f"learned, split by out-degree {dsplit}, k={k}")
+        assert K.kc_count(h, k) == og.count(k), k
+    c, _ = per_root(h, el.n, 5)
+    assert np.array_equal(c, og.count_per_root(5))
+    for g in train + [h]:
+        K.kc_graph_destroy(g)
+
+
 @pytest.mark.parametrize("cache", ["1", "0"])
 @pytest.mark.parametrize("k", [3, 5, 6])
 def test_batch_matches_per_graph(stream, k, cache, monkeypatch):
