@@ -1072,20 +1072,17 @@ __device__ __forceinline__ uint32_t compact_local2(const uint64_t *P, uint32_t l
     return nmem;
 }
 
-// Edges of G+(u) inside the node set C (words lo..W-1, absolute word index):
-// sum over members v of |C n row_v|.  Members are gathered 64 at a time into
-// mem (one per lane), each lane then intersects its member's row with C.
-// (fpart, fparts): only members v with v % fparts == fpart start an edge.
-__device__ __forceinline__ void wide_edges(const uint64_t *C, uint32_t lo, uint32_t W, const uint64_t *bm,
-                                           uint32_t *mem, uint64_t &acc, uint32_t fpart = 0, uint32_t fparts = 1) {
+// Members of the node set C (words lo..W-1, absolute word index) gathered 64 at a
+// time into mem (one per lane); body(k) runs on each full batch and on the last
+// partial one, with lanes 0..k-1 holding members.  (fpart, fparts): only members v
+// with v % fparts == fpart are gathered.
+template <class Body>
+__device__ __forceinline__ void wide_members(const uint64_t *C, uint32_t lo, uint32_t W, uint32_t *mem,
+                                             uint32_t fpart, uint32_t fparts, Body body) {
     const uint32_t lane = kc_lane();
     auto flush = [&](uint32_t k) {
         kc_wave_sync();
-        if (lane < k) {
-            const uint32_t v = mem[lane];
-            const uint64_t *rv = bm_row(bm, v, W);
-            for (uint32_t l = (v + 1) >> 6; l < W; ++l) acc += (uint64_t)__popcll(rv[l] & C[l]);
-        }
+        body(k);
         kc_wave_sync();
     };
     uint32_t cnt = 0;
@@ -1107,6 +1104,51 @@ __device__ __forceinline__ void wide_edges(const uint64_t *C, uint32_t lo, uint3
         }
     }
     if (cnt) flush(cnt);
+}
+
+// Edges of G+(u) inside the node set C: sum over members v of |C n row_v|, each
+// lane intersecting its member's row with C.
+__device__ __forceinline__ void wide_edges(const uint64_t *C, uint32_t lo, uint32_t W, const uint64_t *bm,
+                                           uint32_t *mem, uint64_t &acc, uint32_t fpart = 0, uint32_t fparts = 1) {
+    const uint32_t lane = kc_lane();
+    wide_members(C, lo, W, mem, fpart, fparts, [&](uint32_t k) {
+        if (lane < k) {
+            const uint32_t v = mem[lane];
+            const uint64_t *rv = bm_row(bm, v, W);
+            for (uint32_t l = (v + 1) >> 6; l < W; ++l) acc += (uint64_t)__popcll(rv[l] & C[l]);
+        }
+    });
+}
+
+// Triangles of G+(u) inside the node set C (the count of a set whose members still
+// need three nodes): sum over members v, and over w in C n row_v, of
+// |C n row_v n row_w|.  Each lane takes one member v and walks its w itself, so no
+// step waits for the whole wave.
+__device__ __forceinline__ void wide_triangles(const uint64_t *C, uint32_t lo, uint32_t W, const uint64_t *bm,
+                                               uint32_t *mem, uint64_t &acc, uint32_t fpart = 0,
+                                               uint32_t fparts = 1) {
+    const uint32_t lane = kc_lane();
+    wide_members(C, lo, W, mem, fpart, fparts, [&](uint32_t k) {
+        if (lane < k) {
+            const uint32_t v = mem[lane];
+            const uint64_t *rv = bm_row(bm, v, W);
+            uint32_t c = 0;
+            for (uint32_t l = (v + 1) >> 6; l < W; ++l) {
+                uint64_t x = C[l] & rv[l];
+                while (x) {
+                    const uint32_t w = 64 * l + (uint32_t)__builtin_ctzll(x);
+                    x &= x - 1;
+                    // word l: the members of C n row_v after w are what is left of x;
+                    // row w starts at word (w + 1) / 64, so it is read there only when
+                    // x still holds bits (w is then not the word's last bit)
+                    const uint64_t *rw = bm_row(bm, w, W);
+                    if (x) c += (uint32_t)__popcll(x & rw[l]);
+                    for (uint32_t l3 = l + 1; l3 < W; ++l3) c += (uint32_t)__popcll(C[l3] & rv[l3] & rw[l3]);
+                }
+            }
+            acc += c;
+        }
+    });
 }
 
 // NW waves per block (4, 8 or 16): the waves share the root's bitmap, so a larger
@@ -1385,6 +1427,10 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                     local_count2(A2, sN, K - 2, acc, fpart, fparts);
                     return;
                 }
+                if (K == 5) {
+                    wide_triangles(ri, lo0, W, bm, A.members, acc, fpart, fparts);
+                    return;
+                }
                 // Wide depth-first search.  stk[depth] holds the candidates not yet
                 // visited of a node that still needs K-2-depth nodes; a child that
                 // needs 2 more is counted by wide_edges, one of at most 64 nodes as a
@@ -1440,6 +1486,9 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                     if ((int)cpc < cn) continue;
                     if (cn == 2) {
                         wide_edges(nxt, clo, W, bm, A.members, acc);
+                        kc_wave_sync();
+                    } else if (cn == 3 && cpc > (p.local2 ? 128u : 64u)) {
+                        wide_triangles(nxt, clo, W, bm, A.members, acc);
                         kc_wave_sync();
                     } else if (cpc <= 64) {
                         const uint32_t sN = compact_local(nxt, clo, W, bm, W, A);

@@ -124,11 +124,13 @@ def test_tier_boundaries_complete_graphs():
 @pytest.mark.parametrize("level2", ["1", "2"])
 def test_wide_search_closed_forms(monkeypatch, level2):
     """First-level candidate sets above 128 nodes (the wide depth-first search of the
-    workgroup tier, from k = 5): K_400 and K_300 against C(n, k), and a complete
+    workgroup tier, from k = 5): K_400, K_300 and K_260 against C(n, k) (sets that
+    still need three nodes are counted lane-parallel at the first level at k = 5, one
+    and two levels down at k = 6 and 7), and a complete
     multipartite graph against the elementary symmetric polynomial of its parts; with
     two-level items where the estimate asks for them (1) and for every wide node (2)."""
     monkeypatch.setenv("KC_LEVEL2", level2)
-    for n, ks in [(400, [5]), (300, [6])]:
+    for n, ks in [(400, [5]), (300, [6]), (260, [7])]:
         h = device_graph(S.complete(n))
         for k in ks:
             announce(f"K{n} k={k} (wide search)")
