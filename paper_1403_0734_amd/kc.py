@@ -56,6 +56,13 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"libkc.so not found at {path}: build it with `python -m paper_1403_0734_amd.build`")
+    # PyTorch-ROCm ships its own HIP runtime under the same soname.  Loaded after
+    # libkc.so, it would be a second runtime in the process (device pointers and
+    # streams of one are unknown to the other); loaded first, libkc.so binds to it.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P, i32, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64
     sig = {
