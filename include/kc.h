@@ -229,7 +229,7 @@ typedef struct {
                                    LDS limit when above it) */
     int32_t local_bits;         /* width of the local graphs that candidate sets of workgroup-tier roots
                                    are compacted into, in nodes: 64 (one word per row) or 128 (two
-                                   words; used from k = 5); 0 = 128 */
+                                   words; used from k = 6); 0 = 128 */
     int32_t wg_waves;           /* waves per workgroup-tier block: 4, 8 or 16, or 0 = per launch, the
                                    shape that keeps the most waves resident (LDS, registers) */
 } kc_tuning;

@@ -371,6 +371,7 @@ extern "C" kc_status kc_autotune(kc_graph *const *gs, uint32_t num, int32_t k, c
             for (int c : wvb)
                 for (int d : cds)
                     for (int e : lbs) {
+                        if (k < 6 && e != 64) continue;  // two-word local graphs serve k >= 6 only
                         kc_tuning t{a, b, c, d, 0, e, 0};
                         KC_TRY(kc_set_tuning(&t));
                         KC_TRY(kc_count_batch(gs, num, k, out.data()));  // builds, runs eagerly and captures

@@ -115,7 +115,7 @@ struct CountParams {
     size_t slice_words;   // u64 words per slice
     uint32_t dcap;        // largest d the workgroup layout holds
     uint32_t chunk_div;   // queue chunk = count / (workers * chunk_div)
-    uint32_t local2;      // workgroup tier, k >= 5: compact candidate sets of 65..128 nodes into two-word local graphs
+    uint32_t local2;      // workgroup tier, k >= 6: compact candidate sets of 65..128 nodes into two-word local graphs
     // workgroup tier, split roots: item = rank << 32 | part << 16 | parts (null: queue, one part each)
     const uint64_t *items;
     // batches: graph of every rank and one total per graph (null for one graph)
@@ -908,7 +908,9 @@ __host__ __device__ inline uint64_t tri_words(uint64_t d) {
 }
 
 // static LDS of the workgroup kernel: one local-graph area per wave (two-word
-// areas from k = 5 on, where candidate sets are compacted) plus small arrays
+// areas from k = 6 on, where candidate sets of 65..128 nodes are compacted; at k = 5
+// such a set's count is its triangles, which wide_triangles takes without a local
+// graph, and the one-word areas leave room for more blocks per CU) plus small arrays
 // the workgroup tier counts at most (k-2)-cliques in a local graph: k-5 stack entries
 template <int K>
 struct WgAreas {
@@ -916,7 +918,7 @@ struct WgAreas {
     using A1 = LocalArea<NS>;
     using A2 = LocalArea2<NS>;
 };
-__host__ __device__ constexpr size_t wg_local_bytes_k(int K, size_t a1, size_t a2) { return K >= 5 ? a2 : a1; }
+__host__ __device__ constexpr size_t wg_local_bytes_k(int K, size_t a1, size_t a2) { return K >= 6 ? a2 : a1; }
 template <int K>
 __host__ __device__ constexpr size_t wg_local_bytes() {
     return wg_local_bytes_k(K, sizeof(typename WgAreas<K>::A1), sizeof(typename WgAreas<K>::A2));
@@ -1422,7 +1424,7 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                     local_count<LC_REG_WG, false, false>(A, sN, K - 2, acc, fpart, fparts);
                     return;
                 }
-                if (K >= 5 && p.local2 && pc <= 128) {
+                if (K >= 6 && p.local2 && pc <= 128) {
                     const uint32_t sN = compact_local2(ri, lo0, W, bm, W, A2);
                     local_count2(A2, sN, K - 2, acc, fpart, fparts);
                     return;
@@ -1487,13 +1489,13 @@ __global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
                     if (cn == 2) {
                         wide_edges(nxt, clo, W, bm, A.members, acc);
                         kc_wave_sync();
-                    } else if (cn == 3 && cpc > (p.local2 ? 128u : 64u)) {
+                    } else if (cn == 3 && cpc > (K >= 6 && p.local2 ? 128u : 64u)) {
                         wide_triangles(nxt, clo, W, bm, A.members, acc);
                         kc_wave_sync();
                     } else if (cpc <= 64) {
                         const uint32_t sN = compact_local(nxt, clo, W, bm, W, A);
                         local_count<LC_REG_WG, false, false>(A, sN, cn, acc);
-                    } else if (K >= 5 && p.local2 && cpc <= 128) {
+                    } else if (K >= 6 && p.local2 && cpc <= 128) {
                         const uint32_t sN = compact_local2(nxt, clo, W, bm, W, A2);
                         local_count2(A2, sN, cn, acc);
                     } else {
