@@ -444,7 +444,7 @@ struct LocalArea2 {
     uint64_t rows[128][2];
     uint32_t epre[128];
     uint32_t members[128];
-    uint64_t stk[NS > LC_LDS_FROM ? NS : 1][2][64];
+    uint64_t stk[NS > LC_LDS_FROM ? NS : 0][2][64];  // depth-first stacks when too deep for registers
 };
 
 __device__ __forceinline__ uint32_t select_bit2(uint64_t w0, uint64_t w1, uint32_t r) {
