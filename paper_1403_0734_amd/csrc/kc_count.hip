@@ -1157,8 +1157,15 @@ __device__ __forceinline__ void wide_triangles(const uint64_t *C, uint32_t lo, u
 // block keeps more waves resident when one arena fills most of the LDS.
 // L2: the item list holds two-level items (and roots that leave wide nodes to them);
 // without it the kernel carries none of that code or its registers.
+// Waves per SIMD the register allocation of the workgroup kernel is held to (the
+// compiler's own choice gives 141 VGPRs at k = 8, three waves per SIMD).  Measured on
+// planted 4M: four waves at k = 8 (125 VGPRs, no spill) 235 to 228 ms; five at k = 6
+// and 7 (a few spilled registers) 39.8 / 132 to 36.7 / 129.5 ms, where five cost time
+// at k = 5 (R-MAT 22) and k = 8.
+constexpr int wg_waves_per_eu(int k) { return k == 6 || k == 7 ? 5 : 4; }
 template <int K, bool GLOBAL, int MODE, int NW, bool L2>
-__global__ void __launch_bounds__(NW * 64) k_count_wg(CountParams p) {
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(wg_waves_per_eu(K))))
+k_count_wg(CountParams p) {
     constexpr uint32_t WGT = NW * 64;
     extern __shared__ __align__(16) unsigned char smem_dyn[];
     __shared__ __align__(16) uint64_t s_lraw[NW][wg_local_bytes<K>() / 8];
