@@ -658,8 +658,14 @@ __device__ __forceinline__ void wave_stage_check(WaveSmem<K> &sm, uint32_t qh, u
     }
 }
 
+// Register target of the one-wave kernel: eight waves per SIMD from k = 7 (a few
+// spilled registers; planted 4M one-wave tier k = 7 / 8 4.7 / 15.9 to 3.8 / 12.9 ms),
+// the compiler's own choice below (eight waves there cost Chung-Lu 1M k = 6 0.33 to
+// 0.51 ms).
+constexpr int wave_waves_per_eu(int k) { return k >= 7 ? 8 : 1; }
 template <int K, int MODE>
-__global__ void __launch_bounds__(WG) k_count_wave(CountParams p) {
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(wave_waves_per_eu(K))))
+k_count_wave(CountParams p) {
     __shared__ WaveSmem<K> sm_all[WAVES];
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     WaveSmem<K> &sm = sm_all[wave];
