@@ -1169,6 +1169,10 @@ __device__ __forceinline__ void wide_triangles(const uint64_t *C, uint32_t lo, u
 // and 7 (a few spilled registers) 39.8 / 132 to 36.7 / 129.5 ms, where five cost time
 // at k = 5 (R-MAT 22) and k = 8.
 constexpr int wg_waves_per_eu(int k) { return k == 6 || k == 7 ? 5 : 4; }
+// Chunks of 64 out-list elements a staging wave loads before using them (memory-level
+// parallelism: the pass reads the lists of every member of each G+(u)).  Planted 4M:
+// one chunk 22.1 ms for the workgroup tier's staging, four 17.5 ms.
+constexpr int STAGE_CHUNKS = 4;
 template <int K, bool GLOBAL, int MODE, int NW, bool L2>
 __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(wg_waves_per_eu(K))))
 k_count_wg(CountParams p) {
@@ -1350,7 +1354,9 @@ k_count_wg(CountParams p) {
             if (d > 0) {
                 const uint32_t alast = nb[d - 1];
                 if (Ttot >= 32u * d) {
-                    // long out-lists: one wave per list, coalesced reads, stop past alast
+                    // long out-lists: one wave per list, coalesced reads of STAGE_CHUNKS
+                    // 64-element chunks at a time (as many loads in flight per wave), stop
+                    // past alast
                     for (;;) {
                         uint32_t i = 0;
                         if (lane == 0) i = atomicAdd(&s_misc[3], 1u);
@@ -1359,16 +1365,23 @@ k_count_wg(CountParams p) {
                         const uint64_t b = delta[i] + seg[i];
                         const uint32_t len = seg[i + 1] - seg[i];
                         uint64_t *ri = bm + tri_rowoff(i, W) - ((i + 1) >> 6);
-                        for (uint32_t o = 0; o < len; o += 64) {
-                            const uint32_t t = o + lane;
-                            const uint32_t y = t < len ? p.ocol[b + t] : 0xFFFFFFFFu;
-                            const bool in = y <= alast;
-                            if (!__any(in)) break;  // the list is sorted
-                            if (!in) continue;
-                            const uint32_t j = hash_find(htab, hbits, nb, y);
-                            if (j == HEMPTY) continue;
-                            if (p.colored && p.scheme == KC_COLOR_PER_ROOT && colr[i] != colr[j]) continue;
-                            atomicOr((unsigned long long *)(ri + (j >> 6)), 1ull << (j & 63));
+                        for (uint32_t o = 0; o < len; o += 64u * STAGE_CHUNKS) {
+                            uint32_t y[STAGE_CHUNKS];
+#pragma unroll
+                            for (int c = 0; c < STAGE_CHUNKS; ++c) {
+                                const uint32_t t = o + 64u * c + lane;
+                                y[c] = t < len ? p.ocol[b + t] : 0xFFFFFFFFu;
+                            }
+#pragma unroll
+                            for (int c = 0; c < STAGE_CHUNKS; ++c) {
+                                if (y[c] > alast) continue;
+                                const uint32_t j = hash_find(htab, hbits, nb, y[c]);
+                                if (j == HEMPTY) continue;
+                                if (p.colored && p.scheme == KC_COLOR_PER_ROOT && colr[i] != colr[j]) continue;
+                                atomicOr((unsigned long long *)(ri + (j >> 6)), 1ull << (j & 63));
+                            }
+                            // the list is sorted: the rest lies past alast
+                            if (!__any(y[STAGE_CHUNKS - 1] <= alast)) break;
                         }
                     }
                 } else {
