@@ -1776,14 +1776,16 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
     if (q.count[1]) {
         // Block shape of a launch whose arena holds out-degree dmax: waves per block
         // (4, 8 or 16; the wg_waves tunable fixes it) and resident blocks per CU.  Four
-        // waves per block while at least two such blocks fit on a CU (the waves of a
+        // waves per block while at least four such blocks fit on a CU (the waves of a
         // block share one root or item: small blocks balance better); otherwise the
         // shape with the most waves resident (LDS and registers), at most 32.  One
         // large arena per block (a root of out-degree 1031 takes about 90 KB) leaves
         // room for one block: more waves in it keep the CU busy while others wait on
         // LDS.  Measured: R-MAT 22 at k = 5, 1.98 s with four waves, 1.44 s with the
-        // larger block; planted 4M at k = 8, 349 ms with two four-wave blocks per CU,
-        // 570 ms with one 16-wave block.
+        // larger block; planted 4M at k = 8, the large roots' launch (three four-wave
+        // blocks or two eight-wave blocks per CU): the tier 229 ms with four waves, 204
+        // ms with eight; with two four-wave blocks as the bound, k = 5..7 and R-MAT
+        // unchanged.
         const void *fn[3] = {(const void *)&k_count_wg<K, false, MODE, 4, false>,
                              (const void *)&k_count_wg<K, false, MODE, 8, false>,
                              (const void *)&k_count_wg<K, false, MODE, 16, false>};
@@ -1830,7 +1832,7 @@ void launch_tiers(const CountParams &base, const kc_queue &q, uint32_t *cursors,
                 if (per_cu * (uint32_t)nw > 32u) per_cu = 32u / (uint32_t)nw;
                 if (tu.wg_blocks_per_cu > 0 && (uint32_t)tu.wg_blocks_per_cu < per_cu)
                     per_cu = (uint32_t)tu.wg_blocks_per_cu;
-                if (i == 0 && per_cu >= 2 && !tu.wg_waves) return Shape{0, per_cu};
+                if (i == 0 && per_cu >= 4 && !tu.wg_waves) return Shape{0, per_cu};
                 if (per_cu * (uint32_t)nw > best.per_cu * (uint32_t)nws[best.idx]) best = Shape{i, per_cu};
             }
             if (best.per_cu == 0) best = Shape{0, 1};  // every root of the tier fits four waves' arena
