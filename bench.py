@@ -500,10 +500,10 @@ def bench_batch(args, K, torch, stream):
 
 
 def bench_schedule(args, K, torch, np, G, stream, wpath, train_info):
-    """Plain degree binning (the reference the others are measured against), the edge-estimate items and the learned
-    schedule on the planted-clique Chung-Lu 4M graph: same kernels and counts, only
-    the queue order, tiers and item split differ.  Median of 5 counts after one
-    warm-up count per (policy, k)."""
+    """Plain degree binning (the reference the others are measured against), the
+    edge-estimate items and the learned schedule on the planted-clique Chung-Lu 4M
+    graph: same kernels and counts, only the queue order, tiers and item split
+    differ.  Median of 5 counts after one warm-up count per (policy, k)."""
     ks = [int(x) for x in args.sched_ks.split(",")]
     log("schedule: planted workload")
     el = G.workload_planted()
